@@ -1,0 +1,217 @@
+/*
+ * wcc.h -- C ABI of the MI355X (gfx950) Well-Connected Clusters hot path.
+ *
+ * Method: Dindoost et al., "On the Optimization of Methods for Establishing
+ * Well-Connected Communities", arXiv 2509.02590.
+ *   - CCR, Alg. 1: each input cluster's induced subgraph; when it has edges, its
+ *     connected components larger than s_pre are queued.
+ *   - WCC, Alg. 2, and isWCC, Alg. 3: a queued set whose exact global minimum cut exceeds
+ *     the criterion f(n) of its size (Sec. 2: log10 n, log2 n, sqrt n, or linear k*n) is
+ *     saved; otherwise it is split along the cut and every part larger than s_post is
+ *     processed again.
+ *   - GetMinCut / MinCutPartition, Alg. 3 and Sec. 2.1: the cut and its two sides.
+ *
+ * Conventions shared by every entry point:
+ *   - Graphs are undirected, simple and unweighted, in symmetric CSR form: each edge
+ *     {u,v} is stored once in u's row and once in v's row, no self-loops, no
+ *     duplicates.  The order of entries inside a row does not matter.
+ *   - Every pointer documented "device" is a device allocation owned by the caller.
+ *     The library never frees caller memory; it owns its own workspace, which it
+ *     allocates lazily per device and keeps until wcc_release() or process exit.
+ *   - stream is a hipStream_t passed as void*; NULL means the null stream.  Each call
+ *     enqueues its work on that stream and returns once the documented outputs are
+ *     complete (the calls are blocking).
+ *   - Return value: WCC_OK (0) or one of the negative WCC_E* codes.  No C++ exception
+ *     crosses this boundary.  On error the outputs are unspecified.
+ *   - Calls on the same device are serialised by an internal lock.
+ *
+ * Canonical results (needed for bit-exact comparison, not fixed by the paper):
+ *   - the threshold test "cut > f(n)" is evaluated as cut >= k(n), k(n) the least
+ *     integer above f(n): LOG10 -> decimal digits of n, LOG2 -> bit length of n,
+ *     SQRT -> isqrt(n)+1, LINEAR -> floor(num*n/den)+1;
+ *   - among equal minimum cuts the library returns the one produced by the canonical
+ *     scan-and-contract rule: degree pre-pass, then rounds of maximum-adjacency scans
+ *     from the smallest vertex id with keys capped at the current bound, ties to the
+ *     smallest id, contraction of every edge whose key reaches the bound, and a
+ *     strict-improvement degree check in ascending id order;
+ *   - local ids are ranks of global vertex ids, so "smallest id" means smallest global id;
+ *   - output labels number the saved sets 0..K-1 by ascending smallest global vertex id;
+ *     every other vertex gets -1.
+ */
+#ifndef WCC_H
+#define WCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ error codes */
+#define WCC_OK 0
+#define WCC_EINVAL -1        /* bad argument or parameter */
+#define WCC_EGRAPH -2        /* CSR is not symmetric simple (checked with WCC_FLAG_VALIDATE) */
+#define WCC_ENOMEM -3        /* device workspace could not be allocated */
+#define WCC_EHIP -4          /* a HIP runtime call failed */
+#define WCC_ENOTCONNECTED -5 /* reserved */
+#define WCC_ECANCELLED -6    /* a served job was cancelled */
+#define WCC_ETIMEOUT -7      /* a served job did not finish in time */
+#define WCC_ENODEV -8        /* no HIP device */
+#define WCC_EUNSUPPORTED -9  /* a size or parameter beyond this build's limits */
+
+/* ------------------------------------------------------------------ inputs */
+typedef struct {
+  int64_t num_vertices;    /* N */
+  int64_t num_entries;     /* directed CSR entries, 2m */
+  const void *row_offsets; /* device, N+1 offsets of width offset_bits (32 or 64) */
+  int32_t offset_bits;     /* 32 -> int32_t offsets, 64 -> int64_t offsets */
+  int32_t reserved;
+  const int32_t *col_indices; /* device, num_entries neighbour ids in [0, N) */
+} wcc_csr;
+
+/* Criterion f(n) of Sec. 2. */
+#define WCC_CRIT_LOG10 0
+#define WCC_CRIT_LOG2 1
+#define WCC_CRIT_SQRT 2
+#define WCC_CRIT_LINEAR 3 /* f(n) = lin_num * n / lin_den */
+
+/* Pruning at entry of a queued set. */
+#define WCC_PRUNE_PAPER 0 /* Alg. 1-3 as printed: no pruning */
+#define WCC_PRUNE_KCORE 1 /* a set of size n is replaced by the connected components of its
+                             k(n)-core (larger than s_post) whenever that core is not the
+                             whole set; only whole-core sets are cut */
+
+#define WCC_EXEC_PLAIN 0   /* level-synchronous: one launch per recursion depth */
+#define WCC_EXEC_BATCHED 1 /* persistent work-queue kernel, one launch per job */
+
+#define WCC_FLAG_VALIDATE 1u /* check the CSR first; WCC_EGRAPH if malformed */
+
+typedef struct {
+  int32_t criterion;   /* WCC_CRIT_* (default LOG10) */
+  int32_t lin_num;     /* LINEAR only; lin_num >= 0, lin_den >= 1 */
+  int32_t lin_den;
+  int32_t s_pre;       /* CCR keeps components with size > s_pre (Alg. 1); >= 0 */
+  int32_t s_post;      /* parts with size > s_post are processed again (Alg. 3); >= 0 */
+  int32_t prune_mode;  /* WCC_PRUNE_* */
+  int32_t mincut_rule; /* 1 = the canonical rule above (the only one) */
+  int32_t exec_mode;   /* WCC_EXEC_* */
+  uint32_t flags;      /* WCC_FLAG_* */
+  int32_t reserved;
+} wcc_params;
+
+/* Fills *p with the defaults: LOG10, s_pre = s_post = 10, KCORE, rule 1, PLAIN. */
+void wcc_default_params(wcc_params *p);
+
+/* Per-call counters (host struct, filled on success when non-NULL). */
+typedef struct {
+  int64_t clusters;      /* distinct input cluster ids */
+  int64_t intra_entries; /* directed entries of all induced cluster subgraphs */
+  int64_t items;         /* queued sets processed, clusters included */
+  int64_t mincuts;       /* minimum-cut evaluations */
+  int64_t accepted;      /* saved sets */
+  int64_t levels;        /* recursion depths (launch rounds) */
+  int64_t scan_steps;    /* maximum-adjacency scan steps over all cuts */
+  int64_t scan_rounds;   /* scan-and-contract rounds over all cuts */
+  double ms_front;       /* device time: validation, grouping and compaction */
+  double ms_items;       /* device time: all item launches */
+  double ms_item_kernel; /* summed durations of the item-kernel launches */
+  int64_t item_launches; /* number of item-kernel launches */
+  double ms_total;       /* host wall time of the call */
+} wcc_stats;
+
+/* One record per minimum-cut evaluation (order of records is unspecified). */
+typedef struct {
+  int32_t minv;   /* smallest global vertex id of the set */
+  int32_t n;      /* set size */
+  int32_t k;      /* k(n), used as the cut cap */
+  int32_t lambda; /* returned cut value: exact if below k, else k */
+  int32_t ssize;  /* size of the recorded side S (0 if none) */
+  int32_t reserved;
+  uint64_t shash; /* sum over v in S of splitmix64-finaliser(v + 0x9E3779B97F4A7C15) */
+} wcc_record;
+
+/* ------------------------------------------------------------------ entry points */
+
+/*
+ * wcc_run -- WCC over a whole graph and input clustering (Alg. 1-3).
+ *   g              device CSR of G (N vertices).
+ *   membership_in  device, N int32: input cluster id of each vertex (any non-negative
+ *                  value; clusters are the classes of equal ids) or < 0 for unassigned.
+ *   p              host parameters (NULL = defaults).
+ *   membership_out device, N int32, caller-allocated: canonical label or -1.
+ *   stats          host, nullable.
+ *   records        device, nullable: up to records_cap wcc_record entries; the total
+ *                  number produced is written to *num_records (host, nullable) even
+ *                  when it exceeds records_cap (then only the first records_cap are kept).
+ * Errors: WCC_EINVAL (NULL required pointers, s_pre/s_post < 0, bad criterion, N < 0 or
+ * num_entries inconsistent with offsets), WCC_EGRAPH (with WCC_FLAG_VALIDATE),
+ * WCC_ENOMEM, WCC_EHIP, WCC_EUNSUPPORTED (a cluster with more than 2^24 vertices, or a
+ * cut bound above 62 for SQRT/LINEAR criteria).
+ */
+int wcc_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p,
+            int32_t *membership_out, wcc_stats *stats, wcc_record *records, int64_t records_cap,
+            int64_t *num_records, void *stream);
+
+/*
+ * wcc_mincut_split -- GetMinCut + MinCutPartition (Alg. 3; the CM step of Alg. 5) on the
+ * subgraph of G induced by one vertex set.
+ *   verts   device, n int32 global ids, sorted ascending, unique.
+ *   cap     >= 1: the cut is exact when its value is below cap; otherwise cap is
+ *           returned (pass INT32_MAX for an uncapped exact cut; WCC uses k(n)).
+ *   lambda  host, out: the cut value (0 if the induced subgraph is disconnected or n < 2).
+ *   side    device, n bytes, out: 1 for vertices in S.  A disconnected set returns S =
+ *           the component of verts[0]; n < 2 returns S empty.
+ * Errors: WCC_EINVAL (unsorted/duplicate/out-of-range verts are checked on the device),
+ * WCC_ENOMEM, WCC_EHIP, WCC_EUNSUPPORTED (cap above 62 while the set's minimum degree
+ * also exceeds 62).
+ */
+int wcc_mincut_split(const wcc_csr *g, const int32_t *verts, int32_t n, int32_t cap,
+                     int32_t *lambda, uint8_t *side, void *stream);
+
+/*
+ * wcc_mincut_split_batch -- the same for num_sets pairwise disjoint vertex sets at once.
+ *   verts        device, concatenated sorted unique ids of all sets.
+ *   set_offsets  device, num_sets+1 int64: set i is verts[set_offsets[i] .. set_offsets[i+1]).
+ *   caps         device, num_sets int32 (each >= 1).
+ *   lambdas      device, num_sets int32, out.
+ *   sides        device, set_offsets[num_sets] bytes, out (aligned with verts).
+ * Errors as wcc_mincut_split; overlapping sets give WCC_EINVAL.
+ */
+int wcc_mincut_split_batch(const wcc_csr *g, const int32_t *verts, const int64_t *set_offsets,
+                           int32_t num_sets, const int32_t *caps, int32_t *lambdas,
+                           uint8_t *sides, void *stream);
+
+/*
+ * wcc_cluster_csr -- the membership-filtered compaction alone (the first step of Alg. 1:
+ * E_c = edges with both endpoints in c), exposed for inspection and tests.
+ * Outputs are cluster-major: clusters in ascending cluster id, vertices in ascending id
+ * inside a cluster, each row holding local ids (ranks inside the cluster) in
+ * unspecified order.  Call once with NULL outputs to get the sizes.
+ *   nclusters, nassigned, nentries   host, out.
+ *   cl_ids     device, nclusters int32          cl_start  device, nclusters+1 int64
+ *   vert       device, nassigned int32 global ids
+ *   row_off    device, nassigned+1 int64        adj       device, nentries int32
+ */
+int wcc_cluster_csr(const wcc_csr *g, const int32_t *membership_in, int64_t *nclusters,
+                    int64_t *nassigned, int64_t *nentries, int32_t *cl_ids, int64_t *cl_start,
+                    int32_t *vert, int64_t *row_off, int32_t *adj, void *stream);
+
+/* Threshold k(n) used by the library for the given criterion (host function). */
+int64_t wcc_threshold(int32_t criterion, int64_t n, int32_t lin_num, int32_t lin_den);
+
+/* Human-readable text of an error code (static storage). */
+const char *wcc_strerror(int code);
+
+/* Text describing the last failing HIP call of this thread (empty if none). */
+const char *wcc_last_error_detail(void);
+
+/* Frees the library's workspace on the current device. */
+int wcc_release(void);
+
+/* ABI version of this header: 1. */
+int wcc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCC_H */

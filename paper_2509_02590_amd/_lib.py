@@ -1,0 +1,207 @@
+"""ctypes binding of the gfx950 WCC library (include/wcc.h).
+
+Argument marshalling only: tensors are passed as device pointers with the caller's
+current HIP stream; every step of the computation runs in the library's HIP kernels.
+The library must have been built (paper_2509_02590_amd.build.build()); importing this
+module without it raises ImportError -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libwcc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libwcc.so is not built (%s); run paper_2509_02590_amd.build.build()" % LIB_PATH)
+
+lib = ctypes.CDLL(LIB_PATH)
+
+WCC_OK = 0
+ERRORS = {-1: "EINVAL", -2: "EGRAPH", -3: "ENOMEM", -4: "EHIP", -5: "ENOTCONNECTED",
+          -6: "ECANCELLED", -7: "ETIMEOUT", -8: "ENODEV", -9: "EUNSUPPORTED"}
+CRIT = {"log10": 0, "log2": 1, "sqrt": 2, "linear": 3}
+MODE = {"paper": 0, "kcore": 1}
+EXEC = {"plain": 0, "batched": 1}
+FLAG_VALIDATE = 1
+
+
+class WccError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib.wcc_strerror(code).decode()
+        detail = lib.wcc_last_error_detail().decode() if code == -4 else ""
+        super().__init__("%s: %s (%s) %s" % (what, msg, ERRORS.get(code, code), detail))
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("num_vertices", ctypes.c_int64), ("num_entries", ctypes.c_int64),
+                ("row_offsets", ctypes.c_void_p), ("offset_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("col_indices", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("criterion", ctypes.c_int32), ("lin_num", ctypes.c_int32),
+                ("lin_den", ctypes.c_int32), ("s_pre", ctypes.c_int32),
+                ("s_post", ctypes.c_int32), ("prune_mode", ctypes.c_int32),
+                ("mincut_rule", ctypes.c_int32), ("exec_mode", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("clusters", ctypes.c_int64), ("intra_entries", ctypes.c_int64),
+                ("items", ctypes.c_int64), ("mincuts", ctypes.c_int64),
+                ("accepted", ctypes.c_int64), ("levels", ctypes.c_int64),
+                ("scan_steps", ctypes.c_int64), ("scan_rounds", ctypes.c_int64),
+                ("ms_front", ctypes.c_double), ("ms_items", ctypes.c_double),
+                ("ms_item_kernel", ctypes.c_double), ("item_launches", ctypes.c_int64),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+RECORD_DTYPE = np.dtype([("minv", np.int32), ("n", np.int32), ("k", np.int32),
+                         ("lam", np.int32), ("ssize", np.int32), ("pad", np.int32),
+                         ("shash", np.uint64)])
+
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+lib.wcc_strerror.restype = ctypes.c_char_p
+lib.wcc_strerror.argtypes = [ctypes.c_int]
+lib.wcc_default_params.restype = None
+lib.wcc_default_params.argtypes = [ctypes.POINTER(Params)]
+lib.wcc_run.restype = ctypes.c_int
+lib.wcc_run.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(Params), _vp, ctypes.POINTER(Stats),
+                        _vp, _i64, ctypes.POINTER(ctypes.c_int64), _vp]
+lib.wcc_mincut_split.restype = ctypes.c_int
+lib.wcc_mincut_split.argtypes = [ctypes.POINTER(Csr), _vp, _i32, _i32, ctypes.POINTER(ctypes.c_int32), _vp, _vp]
+lib.wcc_mincut_split_batch.restype = ctypes.c_int
+lib.wcc_mincut_split_batch.argtypes = [ctypes.POINTER(Csr), _vp, _vp, _i32, _vp, _vp, _vp, _vp]
+lib.wcc_cluster_csr.restype = ctypes.c_int
+lib.wcc_cluster_csr.argtypes = [ctypes.POINTER(Csr), _vp] + [ctypes.POINTER(ctypes.c_int64)] * 3 + [_vp] * 6
+lib.wcc_threshold.restype = ctypes.c_int64
+lib.wcc_threshold.argtypes = [_i32, _i64, _i32, _i32]
+lib.wcc_release.restype = ctypes.c_int
+lib.wcc_last_error_detail.restype = ctypes.c_char_p
+lib.wcc_abi_version.restype = ctypes.c_int
+
+
+def _check(rc, what):
+    if rc != WCC_OK:
+        raise WccError(rc, what)
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_csr(offsets, indices) -> Csr:
+    """wcc_csr view of two device tensors (offsets int32/int64 of N+1, indices int32)."""
+    import torch
+    assert offsets.is_cuda and indices.is_cuda, "CSR tensors must be on the GPU"
+    assert offsets.dtype in (torch.int32, torch.int64) and indices.dtype == torch.int32
+    assert offsets.is_contiguous() and indices.is_contiguous()
+    n = offsets.numel() - 1
+    return Csr(n, indices.numel(), offsets.data_ptr() if n >= 0 else None,
+               32 if offsets.dtype == torch.int32 else 64, 0, indices.data_ptr() if indices.numel() else None)
+
+
+def params(criterion="log10", s_pre=10, s_post=10, mode="kcore", exec_mode="plain", lin_num=1,
+           lin_den=1, validate=False) -> Params:
+    p = Params()
+    lib.wcc_default_params(ctypes.byref(p))
+    p.criterion = CRIT[criterion] if isinstance(criterion, str) else criterion
+    p.lin_num, p.lin_den = lin_num, lin_den
+    p.s_pre, p.s_post = s_pre, s_post
+    p.prune_mode = MODE[mode] if isinstance(mode, str) else mode
+    p.exec_mode = EXEC[exec_mode] if isinstance(exec_mode, str) else exec_mode
+    p.flags = FLAG_VALIDATE if validate else 0
+    return p
+
+
+def wcc_run(offsets, indices, membership, *, out=None, records_cap=0, **kw):
+    """WCC over a device CSR and membership -> (membership_out, Stats, records or None)."""
+    import torch
+    g = make_csr(offsets, indices)
+    assert membership.is_cuda and membership.dtype == torch.int32 and membership.numel() == g.num_vertices
+    if out is None:
+        out = torch.empty_like(membership)
+    p = params(**kw)
+    st = Stats()
+    rec = None
+    nrec = ctypes.c_int64(0)
+    if records_cap:
+        rec = torch.empty(records_cap * RECORD_DTYPE.itemsize, dtype=torch.uint8, device=membership.device)
+    rc = lib.wcc_run(ctypes.byref(g), membership.data_ptr() if membership.numel() else None,
+                     ctypes.byref(p), out.data_ptr() if out.numel() else None, ctypes.byref(st),
+                     rec.data_ptr() if rec is not None else None, records_cap, ctypes.byref(nrec),
+                     _stream(torch, membership.device))
+    _check(rc, "wcc_run")
+    records = None
+    if rec is not None:
+        k = min(nrec.value, records_cap)
+        records = np.frombuffer(rec[:k * RECORD_DTYPE.itemsize].cpu().numpy().tobytes(), RECORD_DTYPE)
+        if nrec.value > records_cap:
+            raise WccError(-3, "records buffer too small (%d needed)" % nrec.value)
+    return out, st, records
+
+
+def mincut_split(offsets, indices, verts, cap):
+    """(lambda, side) for the set `verts` (sorted unique device int32)."""
+    import torch
+    g = make_csr(offsets, indices)
+    side = torch.zeros(max(verts.numel(), 1), dtype=torch.uint8, device=verts.device)
+    lam = ctypes.c_int32(0)
+    rc = lib.wcc_mincut_split(ctypes.byref(g), verts.data_ptr() if verts.numel() else None, verts.numel(),
+                              cap, ctypes.byref(lam), side.data_ptr(), _stream(torch, verts.device))
+    _check(rc, "wcc_mincut_split")
+    return lam.value, side[:verts.numel()]
+
+
+def mincut_split_batch(offsets, indices, verts, set_offsets, caps):
+    """(lambdas, sides) for disjoint sets given in CSR-of-sets form on the device."""
+    import torch
+    g = make_csr(offsets, indices)
+    ns = set_offsets.numel() - 1
+    lam = torch.zeros(max(ns, 1), dtype=torch.int32, device=verts.device)
+    sides = torch.zeros(max(verts.numel(), 1), dtype=torch.uint8, device=verts.device)
+    rc = lib.wcc_mincut_split_batch(ctypes.byref(g), verts.data_ptr() if verts.numel() else None,
+                                    set_offsets.data_ptr(), ns, caps.data_ptr() if ns else None,
+                                    lam.data_ptr(), sides.data_ptr(), _stream(torch, verts.device))
+    _check(rc, "wcc_mincut_split_batch")
+    return lam[:ns], sides[:verts.numel()]
+
+
+def cluster_csr(offsets, indices, membership):
+    """Cluster-major induced subgraphs as device tensors (dict)."""
+    import torch
+    g = make_csr(offsets, indices)
+    K, na, E = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    s = _stream(torch, membership.device)
+    rc = lib.wcc_cluster_csr(ctypes.byref(g), membership.data_ptr(), ctypes.byref(K), ctypes.byref(na),
+                             ctypes.byref(E), None, None, None, None, None, s)
+    _check(rc, "wcc_cluster_csr")
+    dev = membership.device
+    cl_ids = torch.empty(max(K.value, 1), dtype=torch.int32, device=dev)
+    cl_start = torch.empty(K.value + 1, dtype=torch.int64, device=dev)
+    vert = torch.empty(max(na.value, 1), dtype=torch.int32, device=dev)
+    row_off = torch.empty(na.value + 1, dtype=torch.int64, device=dev)
+    adj = torch.empty(max(E.value, 1), dtype=torch.int32, device=dev)
+    rc = lib.wcc_cluster_csr(ctypes.byref(g), membership.data_ptr(), ctypes.byref(K), ctypes.byref(na),
+                             ctypes.byref(E), cl_ids.data_ptr(), cl_start.data_ptr(), vert.data_ptr(),
+                             row_off.data_ptr(), adj.data_ptr(), s)
+    _check(rc, "wcc_cluster_csr")
+    return dict(cl_ids=cl_ids[:K.value], cl_start=cl_start, vert=vert[:na.value], row_off=row_off,
+                adj=adj[:E.value])
+
+
+def threshold(n, criterion="log10", lin_num=1, lin_den=1) -> int:
+    c = CRIT[criterion] if isinstance(criterion, str) else criterion
+    return int(lib.wcc_threshold(c, n, lin_num, lin_den))
+
+
+def release():
+    lib.wcc_release()

@@ -1,0 +1,565 @@
+// wcc_capi.hip -- C ABI (include/wcc.h) and host drivers of the gfx950 WCC path.
+//
+// Plain driver (level-synchronous): front end (validate, group, compaction), then one
+// item launch per recursion depth.  Items of a depth are disjoint, so every launch reads
+// one arena and writes the children into the other; the host only learns how many
+// children there are between launches.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "wcc_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------- workspace
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t b) {
+    if (b <= bytes) return WCC_OK;
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t nb = b + b / 8 + 256;
+    if (hipMalloc(&p, nb) != hipSuccess) {
+      (void)hipGetLastError();
+      return WCC_ENOMEM;
+    }
+    bytes = nb;
+    return WCC_OK;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T *as() const {
+    return (T *)p;
+  }
+};
+
+enum BufId {
+  B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_LOCV, B_DEGIN, B_CURSOR,
+  B_ACC, B_MARK, B_RANK, B_TMP, B_DCNT, B_CLSTART, B_CLIDS,
+  B_VTX0, B_VTX1, B_RS0, B_RS1, B_RD0, B_RD1, B_ADJ0, B_ADJ1,
+  B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SEDGE, B_GBITS,
+  B_ITEMS0, B_ITEMS1, B_ITEMS_SORTED, B_SET0, B_SET_SORTED, B_IKEYS, B_IVALS, B_IKEYS2, B_IVALS2,
+  B_SPLITMEM, B_SMALL,
+  B_NUM
+};
+
+struct Workspace {
+  Buf b[B_NUM];
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int cus = 0;
+  void release() {
+    for (auto &x : b) x.release();
+  }
+};
+
+std::mutex g_lock;
+std::vector<Workspace *> g_ws;
+
+int get_ws(Workspace **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1, nullptr);
+  if (!g_ws[dev]) {
+    Workspace *w = new Workspace();
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    w->cus = prop.multiProcessorCount;
+    HIP_TRY(hipEventCreate(&w->ev0));
+    HIP_TRY(hipEventCreate(&w->ev1));
+    g_ws[dev] = w;
+  }
+  *out = g_ws[dev];
+  return WCC_OK;
+}
+
+#define TRY(x)                \
+  do {                        \
+    int _r = (x);             \
+    if (_r != WCC_OK) return _r; \
+  } while (0)
+
+int env_int(const char *name, int dflt) {
+  const char *v = getenv(name);
+  if (!v || !*v) return dflt;
+  return atoi(v);
+}
+
+int check_params(const wcc_params &p) {
+  if (p.criterion < WCC_CRIT_LOG10 || p.criterion > WCC_CRIT_LINEAR) return WCC_EINVAL;
+  if (p.criterion == WCC_CRIT_LINEAR && (p.lin_den < 1 || p.lin_num < 0)) return WCC_EINVAL;
+  if (p.s_pre < 0 || p.s_post < 0) return WCC_EINVAL;
+  if (p.prune_mode != WCC_PRUNE_PAPER && p.prune_mode != WCC_PRUNE_KCORE) return WCC_EINVAL;
+  if (p.mincut_rule != 1) return WCC_EINVAL;
+  if (p.exec_mode != WCC_EXEC_PLAIN && p.exec_mode != WCC_EXEC_BATCHED) return WCC_EINVAL;
+  return WCC_OK;
+}
+
+int check_csr(const wcc_csr *g) {
+  if (!g) return WCC_EINVAL;
+  if (g->num_vertices < 0 || g->num_entries < 0) return WCC_EINVAL;
+  if (g->offset_bits != 32 && g->offset_bits != 64) return WCC_EINVAL;
+  if (g->num_vertices > 0 && !g->row_offsets) return WCC_EINVAL;
+  if (g->num_entries > 0 && !g->col_indices) return WCC_EINVAL;
+  if (g->num_vertices >= (1LL << 31) - 1) return WCC_EUNSUPPORTED;
+  if (g->offset_bits == 32 && g->num_entries >= (1LL << 31)) return WCC_EINVAL;
+  return WCC_OK;
+}
+
+// Front end shared by every entry point: buffers sized for N, grouping, compaction into
+// arena 0.  Outputs na (assigned vertices), K (clusters), E (intra entries).
+struct FrontOut {
+  int64_t na = 0, K = 0, E = 0;
+};
+
+int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate, bool want_ids,
+              FrontOut *fo, hipStream_t s) {
+  int64_t N = g->num_vertices;
+  size_t n4 = (size_t)(N > 0 ? N : 1) * 4;
+  for (int id : {B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_LOCV, B_DEGIN, B_CURSOR,
+                 B_ACC, B_MARK, B_RANK, B_VTX0, B_VTX1, B_RD0, B_RD1, B_SA, B_SB, B_SC, B_SD, B_SE, B_SF})
+    TRY(w.b[id].ensure(n4));
+  TRY(w.b[B_RS0].ensure(2 * n4 + 8));
+  TRY(w.b[B_RS1].ensure(2 * n4 + 8));
+  TRY(w.b[B_CLSTART].ensure(2 * n4 + 16));
+  TRY(w.b[B_CLIDS].ensure(n4));
+  size_t tmpb = prim_radix_tmp_bytes(N > 0 ? N : 1);
+  size_t sb = prim_scan_tmp_bytes(N > 0 ? N : 1);
+  TRY(w.b[B_TMP].ensure(tmpb > sb ? tmpb : sb));
+  TRY(w.b[B_DCNT].ensure(64 * sizeof(unsigned long long)));
+
+  FrontBufs f;
+  f.off = g->row_offsets;
+  f.obits = g->offset_bits;
+  f.idx = g->col_indices;
+  f.mem = mem;
+  f.N = N;
+  f.nnz = g->num_entries;
+  f.keys = w.b[B_KEYS].as<uint32_t>();
+  f.vals = w.b[B_VALS].as<uint32_t>();
+  f.keys2 = w.b[B_KEYS2].as<uint32_t>();
+  f.vals2 = w.b[B_VALS2].as<uint32_t>();
+  f.flag = w.b[B_FLAG].as<int32_t>();
+  f.flag_scan = w.b[B_FLAGSCAN].as<int32_t>();
+  f.cidv = w.b[B_CIDV].as<int32_t>();
+  f.locv = w.b[B_LOCV].as<int32_t>();
+  f.deg_in = w.b[B_DEGIN].as<int32_t>();
+  f.cursor = w.b[B_CURSOR].as<int32_t>();
+  f.tmp = w.b[B_TMP].p;
+  f.tmp_bytes = w.b[B_TMP].bytes;
+  f.dcnt = w.b[B_DCNT].as<unsigned long long>();
+  f.dmax = (int32_t *)(f.dcnt + 8);
+  if (validate) {
+    int ok = 1;
+    TRY(front_validate(f, s, &ok));
+    if (!ok) return WCC_EGRAPH;
+  }
+  TRY(front_group(f, w.b[B_VTX0].as<int32_t>(), w.b[B_CLSTART].as<int64_t>(),
+                  want_ids ? w.b[B_CLIDS].as<int32_t>() : nullptr, &fo->na, &fo->K, s));
+  TRY(front_count(f, w.b[B_VTX0].as<int32_t>(), fo->na, w.b[B_RD0].as<int32_t>(), w.b[B_RS0].as<int64_t>(),
+                  &fo->E, s));
+  size_t e4 = (size_t)(fo->E > 0 ? fo->E : 1) * 4;
+  TRY(w.b[B_ADJ0].ensure(e4));
+  TRY(w.b[B_ADJ1].ensure(e4));
+  TRY(w.b[B_SEDGE].ensure(e4));
+  TRY(front_fill(f, w.b[B_CLSTART].as<int64_t>(), w.b[B_RS0].as<int64_t>(), w.b[B_ADJ0].as<int32_t>(), s));
+  return WCC_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Processes item lists level by level until no children remain.
+int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, const wcc_params &p,
+               int64_t *levels, double *ms_kernel, int64_t *launches, hipStream_t s) {
+  int lds_kb = env_int("WCC_LDS_KB", 32);
+  if (lds_kb < 4) lds_kb = 4;
+  if (lds_kb > 160) lds_kb = 160;
+  size_t lds_bytes = (size_t)lds_kb * 1024;
+  int per_cu = env_int("WCC_WG_PER_CU", 0);
+  if (per_cu <= 0) per_cu = (int)(160 / lds_kb) > 8 ? 8 : (int)(160 / lds_kb);
+  if (per_cu < 1) per_cu = 1;
+  int gmax = w.cus * per_cu;
+  int32_t nitems = nitems0;
+  int cur = 0;  // items in B_ITEMS0 (cur==0) or B_ITEMS1
+  int32_t *dcount = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16);
+  int32_t *dnext = dcount + 1;
+  ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
+  int32_t *set_sorted = base.split_only ? w.b[B_SET_SORTED].as<int32_t>() : nullptr;
+  const int32_t *set_in = base.split_only ? w.b[B_SET0].as<int32_t>() : nullptr;
+  *levels = 0;
+  *ms_kernel = 0;
+  *launches = 0;
+  while (nitems > 0) {
+    ItemDesc *in = w.b[cur ? B_ITEMS1 : B_ITEMS0].as<ItemDesc>();
+    ItemDesc *out = w.b[cur ? B_ITEMS0 : B_ITEMS1].as<ItemDesc>();
+    TRY(items_sort_desc(in, nitems, sorted, set_in, set_sorted, w.b[B_IKEYS].as<uint32_t>(),
+                        w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(), w.b[B_IVALS2].as<uint32_t>(),
+                        w.b[B_TMP].p, w.b[B_TMP].bytes, s, 0));
+    ItemDesc top;
+    HIP_TRY(hipMemcpyAsync(&top, sorted, sizeof(top), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int grid = nitems < gmax ? nitems : gmax;
+    int cap_top = base.split_only ? items_max_level()
+                                  : (int)wcc_k_of(max_cap_crit, top.n, p.lin_num, p.lin_den);
+    int64_t words = items_bitmap_words(top.n, cap_top);
+    TRY(w.b[B_GBITS].ensure((size_t)grid * words * 8 + 64));
+    ItemArgs A = base;
+    A.gbits = w.b[B_GBITS].as<uint64_t>();
+    A.gbits_words = words;
+    A.items = sorted;
+    A.nitems = nitems;
+    A.next = dnext;
+    A.out = out;
+    A.out_count = dcount;
+    A.lds_words = (int32_t)(lds_bytes / 4);
+    if (base.split_only) A.split_set = set_sorted;
+    HIP_TRY(hipMemsetAsync(dcount, 0, 2 * sizeof(int32_t), s));
+    HIP_TRY(hipEventRecord(w.ev0, s));
+    TRY(items_launch(A, grid, lds_bytes, s));
+    HIP_TRY(hipEventRecord(w.ev1, s));
+    int32_t nout = 0;
+    HIP_TRY(hipMemcpyAsync(&nout, dcount, sizeof(nout), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, w.ev0, w.ev1));
+    *ms_kernel += ms;
+    (*launches)++;
+    (*levels)++;
+    if (nout > A.out_cap) return WCC_ENOMEM;
+    long long errc = 0;
+    HIP_TRY(hipMemcpyAsync(&errc, base.cnt + CNT_ERR, sizeof(errc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (errc < 0) return (int)errc;
+    if (base.split_only) break;  // sets are not split further
+    nitems = nout;
+    cur ^= 1;
+  }
+  return WCC_OK;
+}
+
+ItemArgs base_args(Workspace &w, const wcc_params &p, int32_t item_cap) {
+  ItemArgs A;
+  memset(&A, 0, sizeof(A));
+  A.ar[0].vtx = w.b[B_VTX0].as<int32_t>();
+  A.ar[0].rs = w.b[B_RS0].as<int64_t>();
+  A.ar[0].rd = w.b[B_RD0].as<int32_t>();
+  A.ar[0].adj = w.b[B_ADJ0].as<int32_t>();
+  A.ar[1].vtx = w.b[B_VTX1].as<int32_t>();
+  A.ar[1].rs = w.b[B_RS1].as<int64_t>();
+  A.ar[1].rd = w.b[B_RD1].as<int32_t>();
+  A.ar[1].adj = w.b[B_ADJ1].as<int32_t>();
+  A.sA = w.b[B_SA].as<int32_t>();
+  A.sB = w.b[B_SB].as<int32_t>();
+  A.sC = w.b[B_SC].as<int32_t>();
+  A.sD = w.b[B_SD].as<int32_t>();
+  A.sE = w.b[B_SE].as<int32_t>();
+  A.sF = w.b[B_SF].as<int32_t>();
+  A.sEdge = w.b[B_SEDGE].as<int32_t>();
+  A.acc = w.b[B_ACC].as<int32_t>();
+  A.out_cap = item_cap;
+  A.crit = p.criterion;
+  A.lin_num = p.lin_num;
+  A.lin_den = p.lin_den;
+  A.s_pre = p.s_pre;
+  A.s_post = p.s_post;
+  A.mode = p.prune_mode;
+  A.cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  return A;
+}
+
+int ensure_items(Workspace &w, int64_t cap, bool with_sets) {
+  size_t ib = (size_t)(cap > 0 ? cap : 1) * sizeof(ItemDesc);
+  TRY(w.b[B_ITEMS0].ensure(ib));
+  TRY(w.b[B_ITEMS1].ensure(ib));
+  TRY(w.b[B_ITEMS_SORTED].ensure(ib));
+  size_t i4 = (size_t)(cap > 0 ? cap : 1) * 4;
+  for (int id : {B_IKEYS, B_IVALS, B_IKEYS2, B_IVALS2}) TRY(w.b[id].ensure(i4));
+  if (with_sets) {
+    TRY(w.b[B_SET0].ensure(i4));
+    TRY(w.b[B_SET_SORTED].ensure(i4));
+  }
+  return WCC_OK;
+}
+
+int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, int32_t *out, wcc_stats *stats,
+                 wcc_record *rec, int64_t rec_cap, int64_t *nrec, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  wcc_params p;
+  if (pp) p = *pp;
+  else wcc_default_params(&p);
+  TRY(check_params(p));
+  TRY(check_csr(g));
+  if (g->num_vertices > 0 && (!mem_in || !out)) return WCC_EINVAL;
+  if (rec_cap < 0 || (rec_cap > 0 && !rec)) return WCC_EINVAL;
+  int64_t N = g->num_vertices;
+  wcc_stats st;
+  memset(&st, 0, sizeof(st));
+  if (nrec) *nrec = 0;
+  if (N == 0) {
+    if (stats) *stats = st;
+    return WCC_OK;
+  }
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  Workspace &w = *wp;
+  HIP_TRY(hipEventRecord(w.ev0, s));
+  FrontOut fo;
+  TRY(run_front(w, g, mem_in, (p.flags & WCC_FLAG_VALIDATE) != 0, false, &fo, s));
+  HIP_TRY(hipEventRecord(w.ev1, s));
+  HIP_TRY(hipEventSynchronize(w.ev1));
+  float fms = 0;
+  HIP_TRY(hipEventElapsedTime(&fms, w.ev0, w.ev1));
+  st.ms_front = fms;
+  st.clusters = fo.K;
+  st.intra_entries = fo.E;
+  TRY(ensure_items(w, fo.na + 1, false));
+  int32_t *dnitems = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 20);
+  TRY(front_items(w.b[B_CLSTART].as<int64_t>(), fo.K, fo.na, w.b[B_RS0].as<int64_t>(), fo.E,
+                  w.b[B_ITEMS0].as<ItemDesc>(), dnitems, s));
+  HIP_TRY(hipMemsetAsync(w.b[B_ACC].p, 0xff, (size_t)N * 4, s));
+  unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  HIP_TRY(hipMemsetAsync(cnt, 0, CNT_NUM * sizeof(unsigned long long), s));
+  int32_t nitems = 0;
+  HIP_TRY(hipMemcpyAsync(&nitems, dnitems, sizeof(nitems), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  ItemArgs A = base_args(w, p, (int32_t)(fo.na + 1));
+  A.rec = rec;
+  A.rec_cap = rec_cap;
+  auto t1 = std::chrono::steady_clock::now();
+  TRY(run_levels(w, A, nitems, p.criterion, p, &st.levels, &st.ms_item_kernel, &st.item_launches, s));
+  TRY(items_relabel(w.b[B_ACC].as<int32_t>(), N, w.b[B_MARK].as<int32_t>(), w.b[B_RANK].as<int32_t>(), out,
+                    w.b[B_TMP].p, w.b[B_TMP].bytes, s));
+  unsigned long long hc[CNT_NUM];
+  HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  st.ms_items = ms_since(t1);
+  st.items = (int64_t)hc[CNT_ITEMS];
+  st.mincuts = (int64_t)hc[CNT_MINCUTS];
+  st.accepted = (int64_t)hc[CNT_ACCEPTED];
+  st.scan_steps = (int64_t)hc[CNT_STEPS];
+  st.scan_rounds = (int64_t)hc[CNT_ROUNDS];
+  if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
+  st.ms_total = ms_since(t0);
+  if (stats) *stats = st;
+  return WCC_OK;
+}
+
+int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_offsets, int32_t num_sets,
+                     const int32_t *caps, int32_t *lambdas, uint8_t *sides, int64_t nv, hipStream_t s) {
+  TRY(check_csr(g));
+  if (num_sets < 0) return WCC_EINVAL;
+  if (num_sets == 0) return WCC_OK;
+  if (!set_offsets || !caps || !lambdas) return WCC_EINVAL;
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  Workspace &w = *wp;
+  int64_t N = g->num_vertices;
+  TRY(w.b[B_SPLITMEM].ensure((size_t)(N > 0 ? N : 1) * 4));
+  TRY(w.b[B_DCNT].ensure(64 * sizeof(unsigned long long)));
+  HIP_TRY(hipMemsetAsync(lambdas, 0, (size_t)num_sets * 4, s));
+  if (nv > 0) HIP_TRY(hipMemsetAsync(sides, 0, (size_t)nv, s));
+  if (nv == 0) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return WCC_OK;
+  }
+  if (!verts || !sides) return WCC_EINVAL;
+  int32_t *mem = w.b[B_SPLITMEM].as<int32_t>();
+  unsigned long long *bad = w.b[B_DCNT].as<unsigned long long>() + 48;
+  TRY(front_split_membership(verts, set_offsets, num_sets, nv, N, mem, bad, s));
+  unsigned long long hb = 0;
+  HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hb) return WCC_EINVAL;
+  FrontOut fo;
+  TRY(run_front(w, g, mem, false, true, &fo, s));
+  TRY(ensure_items(w, fo.K + 1, true));
+  TRY(front_split_items(w.b[B_CLSTART].as<int64_t>(), w.b[B_CLIDS].as<int32_t>(), fo.K, fo.na,
+                        w.b[B_RS0].as<int64_t>(), fo.E, w.b[B_ITEMS0].as<ItemDesc>(), w.b[B_SET0].as<int32_t>(), s));
+  wcc_params p;
+  wcc_default_params(&p);
+  ItemArgs A = base_args(w, p, (int32_t)(fo.K + 1));
+  unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  HIP_TRY(hipMemsetAsync(cnt, 0, CNT_NUM * sizeof(unsigned long long), s));
+  A.split_only = 1;
+  A.split_lambda = lambdas;
+  A.split_side = sides;
+  A.split_cap = caps;
+  A.split_pos = set_offsets;
+  int64_t lv;
+  double ms;
+  int64_t launches;
+  TRY(run_levels(w, A, (int32_t)fo.K, WCC_CRIT_LOG10, p, &lv, &ms, &launches, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return WCC_OK;
+}
+
+}  // namespace
+
+static thread_local char g_detail[512] = "";
+
+void wcc_note_hip_error(hipError_t e, const char *expr, const char *file, int line) {
+  const char *base = strrchr(file, '/');
+  snprintf(g_detail, sizeof(g_detail), "%s (%d) at %s:%d: %s", hipGetErrorString(e), (int)e,
+           base ? base + 1 : file, line, expr);
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+const char *wcc_last_error_detail(void) { return g_detail; }
+
+void wcc_default_params(wcc_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->criterion = WCC_CRIT_LOG10;
+  p->lin_num = 1;
+  p->lin_den = 1;
+  p->s_pre = 10;
+  p->s_post = 10;
+  p->prune_mode = WCC_PRUNE_KCORE;
+  p->mincut_rule = 1;
+  p->exec_mode = WCC_EXEC_PLAIN;
+  p->flags = 0;
+}
+
+int wcc_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, int32_t *membership_out,
+            wcc_stats *stats, wcc_record *records, int64_t records_cap, int64_t *num_records, void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    return wcc_run_impl(g, membership_in, p, membership_out, stats, records, records_cap, num_records,
+                        (hipStream_t)stream);
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int wcc_mincut_split_batch(const wcc_csr *g, const int32_t *verts, const int64_t *set_offsets, int32_t num_sets,
+                           const int32_t *caps, int32_t *lambdas, uint8_t *sides, void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    if (num_sets < 0) return WCC_EINVAL;
+    if (num_sets == 0) return WCC_OK;
+    if (!set_offsets) return WCC_EINVAL;
+    int64_t nv = 0;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(&nv, set_offsets + num_sets, sizeof(nv), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (nv < 0) return WCC_EINVAL;
+    return split_batch_impl(g, verts, set_offsets, num_sets, caps, lambdas, sides, nv, s);
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int wcc_mincut_split(const wcc_csr *g, const int32_t *verts, int32_t n, int32_t cap, int32_t *lambda,
+                     uint8_t *side, void *stream) {
+  if (!lambda || n < 0 || cap < 1) return WCC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(g_lock);
+    try {
+      Workspace *wp;
+      rc = get_ws(&wp);
+      if (rc) return rc;
+      rc = wp->b[B_SMALL].ensure(64);
+      if (rc) return rc;
+      int64_t *so = wp->b[B_SMALL].as<int64_t>();
+      int64_t hso[2] = {0, n};
+      int32_t hcap = cap;
+      HIP_TRY(hipMemcpyAsync(so, hso, sizeof(hso), hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(so + 2, &hcap, sizeof(hcap), hipMemcpyHostToDevice, s));
+      int32_t *dl = (int32_t *)(so + 3);
+      rc = split_batch_impl(g, verts, so, 1, (const int32_t *)(so + 2), dl, side, n, s);
+      if (rc) return rc;
+      HIP_TRY(hipMemcpyAsync(lambda, dl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    } catch (...) {
+      return WCC_ENOMEM;
+    }
+  }
+  return rc;
+}
+
+int wcc_cluster_csr(const wcc_csr *g, const int32_t *membership_in, int64_t *nclusters, int64_t *nassigned,
+                    int64_t *nentries, int32_t *cl_ids, int64_t *cl_start, int32_t *vert, int64_t *row_off,
+                    int32_t *adj, void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    int rc = check_csr(g);
+    if (rc) return rc;
+    if (!nclusters || !nassigned || !nentries) return WCC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    *nclusters = *nassigned = *nentries = 0;
+    if (g->num_vertices == 0) return WCC_OK;
+    if (!membership_in) return WCC_EINVAL;
+    Workspace *wp;
+    TRY(get_ws(&wp));
+    Workspace &w = *wp;
+    FrontOut fo;
+    TRY(run_front(w, g, membership_in, false, true, &fo, s));
+    *nclusters = fo.K;
+    *nassigned = fo.na;
+    *nentries = fo.E;
+    if (cl_ids && fo.K > 0) HIP_TRY(hipMemcpyAsync(cl_ids, w.b[B_CLIDS].p, fo.K * 4, hipMemcpyDeviceToDevice, s));
+    if (cl_start) HIP_TRY(hipMemcpyAsync(cl_start, w.b[B_CLSTART].p, (fo.K + 1) * 8, hipMemcpyDeviceToDevice, s));
+    if (vert && fo.na > 0) HIP_TRY(hipMemcpyAsync(vert, w.b[B_VTX0].p, fo.na * 4, hipMemcpyDeviceToDevice, s));
+    if (row_off) {
+      if (fo.na > 0) HIP_TRY(hipMemcpyAsync(row_off, w.b[B_RS0].p, fo.na * 8, hipMemcpyDeviceToDevice, s));
+      int64_t E = fo.E;
+      HIP_TRY(hipMemcpyAsync(row_off + fo.na, &E, 8, hipMemcpyHostToDevice, s));
+    }
+    if (adj && fo.E > 0) HIP_TRY(hipMemcpyAsync(adj, w.b[B_ADJ0].p, fo.E * 4, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return WCC_OK;
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int64_t wcc_threshold(int32_t criterion, int64_t n, int32_t lin_num, int32_t lin_den) {
+  if (criterion < WCC_CRIT_LOG10 || criterion > WCC_CRIT_LINEAR) return -1;
+  if (criterion == WCC_CRIT_LINEAR && (lin_den < 1 || lin_num < 0)) return -1;
+  return wcc_k_of(criterion, n, lin_num, lin_den);
+}
+
+const char *wcc_strerror(int code) {
+  switch (code) {
+    case WCC_OK: return "ok";
+    case WCC_EINVAL: return "invalid argument";
+    case WCC_EGRAPH: return "malformed graph (CSR not symmetric simple)";
+    case WCC_ENOMEM: return "out of device memory";
+    case WCC_EHIP: return "HIP runtime error";
+    case WCC_ENOTCONNECTED: return "set not connected";
+    case WCC_ECANCELLED: return "cancelled";
+    case WCC_ETIMEOUT: return "timed out";
+    case WCC_ENODEV: return "no HIP device";
+    case WCC_EUNSUPPORTED: return "size or parameter beyond this build's limits";
+  }
+  return "unknown error";
+}
+
+int wcc_release(void) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return WCC_EHIP;
+  if (dev < (int)g_ws.size() && g_ws[dev]) g_ws[dev]->release();
+  return WCC_OK;
+}
+
+int wcc_abi_version(void) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,462 @@
+// wcc_front.hip -- the front end of the WCC path on gfx950:
+//   * CSR validation (optional),
+//   * grouping of vertices by input cluster (stable radix sort on the cluster id, so
+//     vertices stay in ascending id inside a cluster: local id = rank, Alg. 1 V_c),
+//   * membership-filtered CSR compaction: every cluster's induced subgraph
+//     E_c = {(u,v) in E : u, v in V_c} (Alg. 1, Alg. 2, Alg. 3) with local ids, laid out
+//     cluster-major in arena 0,
+//   * the initial item list (clusters with at least one induced edge, Alg. 1).
+//
+// Entry-parallel passes walk the input CSR in tiles of consecutive entries; each tile
+// finds the rows it covers with one binary search and then locates every entry's row in
+// LDS, so hub rows and short rows cost the same per entry and index loads are coalesced.
+#include "wcc_internal.h"
+
+namespace {
+
+constexpr int FB = 256;             // block
+constexpr int FITEMS = 8;           // entries per thread per tile
+constexpr int FTILE = FB * FITEMS;  // entries per tile
+constexpr int FROWS = FTILE + 1;    // row offsets cached per tile
+
+template <typename OT>
+DEV int64_t row_of(const OT *off, int64_t lo, int64_t hi, int64_t e) {
+  // largest r in [lo, hi] with off[r] <= e
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if ((int64_t)off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per tile: the range of rows [r0, r1] covering entries [e0, e1) and, when it fits, their
+// offsets in LDS.  Returns true when cached.
+template <typename OT>
+DEV bool tile_rows(const OT *off, int64_t N, int64_t e0, int64_t e1, int64_t *sh_r, int64_t *cache) {
+  if (threadIdx.x == 0) sh_r[0] = row_of(off, 0, N - 1, e0);
+  if (threadIdx.x == 1) sh_r[1] = row_of(off, 0, N - 1, e1 - 1);
+  __syncthreads();
+  int64_t r0 = sh_r[0], r1 = sh_r[1];
+  bool cached = (r1 - r0 + 2) <= FROWS;
+  if (cached)
+    for (int64_t i = threadIdx.x; i < r1 - r0 + 2; i += FB) cache[i] = (int64_t)off[r0 + i];
+  __syncthreads();
+  return cached;
+}
+
+DEV int64_t row_in_cache(const int64_t *cache, int64_t nr, int64_t e) {
+  int64_t lo = 0, hi = nr - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (cache[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- validation
+template <typename OT>
+__global__ void __launch_bounds__(FB) k_validate_offsets(const OT *off, int64_t N, int64_t nnz,
+                                                         unsigned long long *bad) {
+  int64_t i = (int64_t)blockIdx.x * FB + threadIdx.x;
+  if (i > N) return;
+  bool b = false;
+  if (i == 0) b = off[0] != 0;
+  else b = off[i] < off[i - 1];
+  if (i == N) b = b || (int64_t)off[N] != nnz;
+  if (b) atomicAdd(&bad[0], 1ull);
+}
+
+DEV uint64_t pair_mix(uint64_t a, uint64_t b) {
+  uint64_t z = a * 0x9E3779B97F4A7C15ULL + b + 0x632BE59BD9B4E019ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// bad[1]: out-of-range or self-loop entries; bad[2]: sum of h(v,u) - h(u,v) over all
+// entries (zero for a symmetric entry multiset, up to a 2^-64 collision chance).
+template <typename OT>
+__global__ void __launch_bounds__(FB) k_validate_entries(const OT *off, const int32_t *idx, int64_t N,
+                                                         int64_t nnz, unsigned long long *bad) {
+  __shared__ int64_t sh_r[2];
+  __shared__ int64_t cache[FROWS];
+  int64_t e0 = (int64_t)blockIdx.x * FTILE, e1 = e0 + FTILE < nnz ? e0 + FTILE : nnz;
+  bool cached = tile_rows(off, N, e0, e1, sh_r, cache);
+  int64_t r0 = sh_r[0], r1 = sh_r[1];
+  unsigned long long nb = 0, h = 0;
+  for (int i = 0; i < FITEMS; i++) {
+    int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
+    if (e >= e1) break;
+    int64_t v = cached ? r0 + row_in_cache(cache, r1 - r0 + 2, e) : row_of(off, r0, r1, e);
+    int32_t u = idx[e];
+    if (u < 0 || u >= N || u == v) nb++;
+    h += pair_mix((uint64_t)v, (uint64_t)(uint32_t)u) - pair_mix((uint64_t)(uint32_t)u, (uint64_t)v);
+  }
+  if (nb) atomicAdd(&bad[1], nb);
+  if (h) atomicAdd(&bad[2], h);
+}
+
+// ---------------------------------------------------------------- grouping
+__global__ void k_member_stats(const int32_t *mem, int64_t N, int32_t *maxid, unsigned long long *na) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t m = -1;
+  int c = 0;
+  if (i < N) {
+    m = mem[i];
+    c = m >= 0;
+  }
+  int s = wave_sum(c);
+  int32_t mx = m;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    int32_t t = __shfl_xor(mx, d, 64);
+    mx = t > mx ? t : mx;
+  }
+  if (__lane_id() == 0) {
+    if (s) atomicAdd(na, (unsigned long long)s);
+    if (mx >= 0) atomicMax(maxid, mx);
+  }
+}
+
+__global__ void k_sort_init(const int32_t *mem, int64_t N, uint32_t unassigned_key, uint32_t *keys,
+                            uint32_t *vals) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int32_t m = mem[i];
+  keys[i] = m >= 0 ? (uint32_t)m : unassigned_key;
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_cluster_flags(const uint32_t *keys, int64_t na, int32_t *flag) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= na) return;
+  flag[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0;
+}
+
+// cid = exclusive-scan(flag) + flag - 1 ; record cluster starts and per-vertex tables
+__global__ void k_cluster_tables(const uint32_t *keys, const uint32_t *vals, const int32_t *flag,
+                                 const int32_t *flag_scan, int64_t na, int64_t *cl_start,
+                                 int32_t *cl_ids, int32_t *cidv, int32_t *locv, int32_t *vtx0) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= na) return;
+  int32_t c = flag_scan[p] + flag[p] - 1;
+  uint32_t v = vals[p];
+  if (flag[p]) {
+    cl_start[c] = p;
+    if (cl_ids) cl_ids[c] = (int32_t)keys[p];
+  }
+  cidv[v] = c;
+  vtx0[p] = (int32_t)v;
+}
+
+__global__ void k_cluster_locals(const int32_t *vtx0, const int32_t *cidv, const int64_t *cl_start,
+                                 int64_t na, int32_t *locv) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= na) return;
+  int32_t v = vtx0[p];
+  locv[v] = (int32_t)(p - cl_start[cidv[v]]);
+}
+
+// ---------------------------------------------------------------- compaction
+// deg_in[v] = number of neighbours of v inside v's cluster
+template <typename OT>
+__global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t *idx, int64_t N,
+                                                    int64_t nnz, const int32_t *cidv, int32_t *deg_in) {
+  __shared__ int64_t sh_r[2];
+  __shared__ int64_t cache[FROWS];
+  __shared__ int cnt[FROWS];
+  int64_t e0 = (int64_t)blockIdx.x * FTILE, e1 = e0 + FTILE < nnz ? e0 + FTILE : nnz;
+  bool cached = tile_rows(off, N, e0, e1, sh_r, cache);
+  int64_t r0 = sh_r[0], r1 = sh_r[1];
+  if (cached)
+    for (int64_t i = threadIdx.x; i < r1 - r0 + 1; i += FB) cnt[i] = 0;
+  __syncthreads();
+  for (int i = 0; i < FITEMS; i++) {
+    int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
+    if (e >= e1) break;
+    int64_t r = cached ? row_in_cache(cache, r1 - r0 + 2, e) : row_of(off, r0, r1, e) - r0;
+    int64_t v = r0 + r;
+    int32_t cv = cidv[v];
+    if (cv < 0) continue;
+    int32_t u = idx[e];
+    if (cidv[u] == cv) {
+      if (cached) atomicAdd(&cnt[r], 1);
+      else atomicAdd(&deg_in[v], 1);
+    }
+  }
+  __syncthreads();
+  if (cached)
+    for (int64_t i = threadIdx.x; i < r1 - r0 + 1; i += FB)
+      if (cnt[i]) atomicAdd(&deg_in[r0 + i], cnt[i]);
+}
+
+__global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t na, int32_t *rd0,
+                             int64_t *rs0) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= na) return;
+  int32_t d = deg_in[vtx0[p]];
+  rd0[p] = d;
+  rs0[p] = d;
+}
+
+// adj0[rs0[pos(v)] + slot] = local id of each intra neighbour; slots from a per-row cursor
+template <typename OT>
+__global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t *idx, int64_t N,
+                                                   int64_t nnz, const int32_t *cidv,
+                                                   const int32_t *locv, const int64_t *cl_start,
+                                                   const int64_t *rs0, int32_t *cursor,
+                                                   int32_t *adj0) {
+  __shared__ int64_t sh_r[2];
+  __shared__ int64_t cache[FROWS];
+  int64_t e0 = (int64_t)blockIdx.x * FTILE, e1 = e0 + FTILE < nnz ? e0 + FTILE : nnz;
+  bool cached = tile_rows(off, N, e0, e1, sh_r, cache);
+  int64_t r0 = sh_r[0], r1 = sh_r[1];
+  for (int i = 0; i < FITEMS; i++) {
+    int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
+    if (e >= e1) break;
+    int64_t v = cached ? r0 + row_in_cache(cache, r1 - r0 + 2, e) : row_of(off, r0, r1, e);
+    int32_t cv = cidv[v];
+    if (cv < 0) continue;
+    int32_t u = idx[e];
+    if (cidv[u] != cv) continue;
+    int64_t pv = cl_start[cv] + locv[v];
+    int32_t slot = atomicAdd(&cursor[v], 1);
+    adj0[rs0[pv] + slot] = locv[u];
+  }
+}
+
+__global__ void k_make_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0,
+                             int64_t E, ItemDesc *items, int32_t *nitems) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  int64_t b = cl_start[c];
+  int64_t e = c + 1 < K ? cl_start[c + 1] : na;
+  int64_t eb = rs0[b];
+  int64_t ee = e < na ? rs0[e] : E;
+  if (ee == eb) return;  // Alg. 1: clusters without induced edges are not refined
+  ItemDesc d;
+  d.b = (int32_t)b;
+  d.n = (int32_t)(e - b);
+  d.eb = eb;
+  d.m = ee - eb;
+  d.depth = 0;
+  d.flags = ITEM_CCR;
+  int32_t slot = atomicAdd(nitems, 1);
+  items[slot] = d;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- host wrappers
+int front_validate(const FrontBufs &f, hipStream_t s, int *ok) {
+  HIP_TRY(hipMemsetAsync(f.dcnt, 0, 4 * sizeof(unsigned long long), s));
+  unsigned gb = nblk(f.N + 1, FB), ge = nblk(f.nnz, FTILE);
+  if (f.obits == 32) {
+    hipLaunchKernelGGL(k_validate_offsets<int32_t>, dim3(gb), dim3(FB), 0, s, (const int32_t *)f.off,
+                       f.N, f.nnz, f.dcnt);
+  } else {
+    hipLaunchKernelGGL(k_validate_offsets<int64_t>, dim3(gb), dim3(FB), 0, s, (const int64_t *)f.off,
+                       f.N, f.nnz, f.dcnt);
+  }
+  unsigned long long h[4];
+  HIP_TRY(hipMemcpyAsync(h, f.dcnt, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[0]) {
+    *ok = 0;
+    return WCC_OK;
+  }
+  if (f.nnz > 0 && f.N > 0) {
+    if (f.obits == 32)
+      hipLaunchKernelGGL(k_validate_entries<int32_t>, dim3(ge), dim3(FB), 0, s,
+                         (const int32_t *)f.off, f.idx, f.N, f.nnz, f.dcnt);
+    else
+      hipLaunchKernelGGL(k_validate_entries<int64_t>, dim3(ge), dim3(FB), 0, s,
+                         (const int64_t *)f.off, f.idx, f.N, f.nnz, f.dcnt);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h, f.dcnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  *ok = (h[1] == 0 && h[2] == 0);
+  return WCC_OK;
+}
+
+// Groups vertices by cluster.  Outputs: *na assigned vertices, *K clusters, vtx0[na]
+// (global ids, cluster-major ascending), cl_start[K+1], cl_ids[K] (nullable), per-vertex
+// cidv/locv (cidv = -1 for unassigned).
+int front_group(const FrontBufs &f, int32_t *vtx0, int64_t *cl_start, int32_t *cl_ids, int64_t *na_out,
+                int64_t *K_out, hipStream_t s) {
+  int64_t N = f.N;
+  HIP_TRY(hipMemsetAsync(f.dcnt, 0, sizeof(unsigned long long), s));
+  HIP_TRY(hipMemsetAsync(f.dmax, 0xff, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_member_stats, dim3(nblk(N, 256)), dim3(256), 0, s, f.mem, N, f.dmax, f.dcnt);
+  HIP_TRY(hipGetLastError());
+  unsigned long long na = 0;
+  int32_t maxid = -1;
+  HIP_TRY(hipMemcpyAsync(&na, f.dcnt, sizeof(na), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&maxid, f.dmax, sizeof(maxid), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *na_out = (int64_t)na;
+  HIP_TRY(hipMemsetAsync(f.cidv, 0xff, (size_t)N * sizeof(int32_t), s));
+  if (na == 0) {
+    *K_out = 0;
+    HIP_TRY(hipMemsetAsync(cl_start, 0, sizeof(int64_t), s));
+    return WCC_OK;
+  }
+  int bits = 0;
+  while (bits < 32 && ((uint64_t)maxid + 1) >> bits) bits++;  // bit length of maxid + 1
+  uint32_t unassigned = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1);
+  hipLaunchKernelGGL(k_sort_init, dim3(nblk(N, 256)), dim3(256), 0, s, f.mem, N, unassigned, f.keys,
+                     f.vals);
+  HIP_TRY(hipGetLastError());
+  int alt = 0;
+  int rc = prim_radix_sort_pairs(f.keys, f.vals, f.keys2, f.vals2, N, bits, f.tmp, f.tmp_bytes, s, &alt);
+  if (rc) return rc;
+  const uint32_t *keys = alt ? f.keys2 : f.keys;
+  const uint32_t *vals = alt ? f.vals2 : f.vals;
+  hipLaunchKernelGGL(k_cluster_flags, dim3(nblk(na, 256)), dim3(256), 0, s, keys, (int64_t)na, f.flag);
+  int32_t *Kdev = (int32_t *)(f.dcnt + 1);
+  rc = prim_excl_scan_i32(f.flag, f.flag_scan, (int64_t)na, Kdev, f.tmp, f.tmp_bytes, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_cluster_tables, dim3(nblk(na, 256)), dim3(256), 0, s, keys, vals, f.flag,
+                     f.flag_scan, (int64_t)na, cl_start, cl_ids, f.cidv, f.locv, vtx0);
+  hipLaunchKernelGGL(k_cluster_locals, dim3(nblk(na, 256)), dim3(256), 0, s, vtx0, f.cidv, cl_start,
+                     (int64_t)na, f.locv);
+  HIP_TRY(hipGetLastError());
+  int32_t K = 0;
+  HIP_TRY(hipMemcpyAsync(&K, Kdev, sizeof(K), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t na64 = (int64_t)na;
+  HIP_TRY(hipMemcpyAsync(cl_start + K, &na64, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  *K_out = K;
+  return WCC_OK;
+}
+
+// Counting pass of the compaction: rd0[p] (intra degree of position p) and rs0[p]
+// (exclusive prefix); *E_out = total intra entries.
+int front_count(const FrontBufs &f, const int32_t *vtx0, int64_t na, int32_t *rd0, int64_t *rs0,
+                int64_t *E_out, hipStream_t s) {
+  HIP_TRY(hipMemsetAsync(f.deg_in, 0, (size_t)f.N * sizeof(int32_t), s));
+  if (f.nnz > 0) {
+    unsigned g = nblk(f.nnz, FTILE);
+    if (f.obits == 32)
+      hipLaunchKernelGGL(k_count_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
+                         f.N, f.nnz, f.cidv, f.deg_in);
+    else
+      hipLaunchKernelGGL(k_count_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
+                         f.N, f.nnz, f.cidv, f.deg_in);
+    HIP_TRY(hipGetLastError());
+  }
+  if (na == 0) {
+    *E_out = 0;
+    return WCC_OK;
+  }
+  hipLaunchKernelGGL(k_gather_deg, dim3(nblk(na, 256)), dim3(256), 0, s, vtx0, f.deg_in, na, rd0, rs0);
+  HIP_TRY(hipGetLastError());
+  int64_t *Edev = (int64_t *)(f.dcnt + 2);
+  int rc = prim_excl_scan_i64(rs0, rs0, na, Edev, f.tmp, f.tmp_bytes, s);
+  if (rc) return rc;
+  int64_t E = 0;
+  HIP_TRY(hipMemcpyAsync(&E, Edev, sizeof(E), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *E_out = E;
+  return WCC_OK;
+}
+
+// Fill pass of the compaction into adj0 (E entries).
+int front_fill(const FrontBufs &f, const int64_t *cl_start, const int64_t *rs0, int32_t *adj0, hipStream_t s) {
+  HIP_TRY(hipMemsetAsync(f.cursor, 0, (size_t)f.N * sizeof(int32_t), s));
+  if (f.nnz > 0) {
+    unsigned g = nblk(f.nnz, FTILE);
+    if (f.obits == 32)
+      hipLaunchKernelGGL(k_fill_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
+                         f.N, f.nnz, f.cidv, f.locv, cl_start, rs0, f.cursor, adj0);
+    else
+      hipLaunchKernelGGL(k_fill_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
+                         f.N, f.nnz, f.cidv, f.locv, cl_start, rs0, f.cursor, adj0);
+    HIP_TRY(hipGetLastError());
+  }
+  return WCC_OK;
+}
+
+int front_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0, int64_t E,
+                ItemDesc *items, int32_t *nitems_dev, hipStream_t s) {
+  HIP_TRY(hipMemsetAsync(nitems_dev, 0, sizeof(int32_t), s));
+  if (K > 0)
+    hipLaunchKernelGGL(k_make_items, dim3(nblk(K, 256)), dim3(256), 0, s, cl_start, K, na, rs0, E, items,
+                       nitems_dev);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
+
+namespace {
+
+// membership for caller sets: mem[v] = set index; bad counts unsorted, duplicate,
+// out-of-range or overlapping entries and malformed offsets
+__global__ void k_split_membership(const int32_t *verts, const int64_t *so, int32_t ns, int64_t nv, int64_t N,
+                                   int32_t *mem, unsigned long long *bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) {
+    if (so[i + 1] < so[i]) atomicAdd(bad, 1ull);
+    if (i == 0 && so[0] != 0) atomicAdd(bad, 1ull);
+  }
+  if (i >= nv) return;
+  int64_t lo = 0, hi = ns - 1;
+  while (lo < hi) {  // set containing entry i: largest s with so[s] <= i
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (so[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  int32_t v = verts[i];
+  if (v < 0 || v >= N) {
+    atomicAdd(bad, 1ull);
+    return;
+  }
+  if (i > so[lo] && verts[i - 1] >= v) atomicAdd(bad, 1ull);
+  if (atomicCAS(&mem[v], -1, (int32_t)lo) != -1) atomicAdd(bad, 1ull);
+}
+
+__global__ void k_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K, int64_t na,
+                              const int64_t *rs0, int64_t E, ItemDesc *items, int32_t *item_set) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  int64_t b = cl_start[c];
+  int64_t e = c + 1 < K ? cl_start[c + 1] : na;
+  int64_t eb = rs0[b];
+  int64_t ee = e < na ? rs0[e] : E;
+  ItemDesc d;
+  d.b = (int32_t)b;
+  d.n = (int32_t)(e - b);
+  d.eb = eb;
+  d.m = ee - eb;
+  d.depth = 0;
+  d.flags = 0;
+  items[c] = d;
+  item_set[c] = cl_ids[c];
+}
+
+}  // namespace
+
+int front_split_membership(const int32_t *verts, const int64_t *set_offsets, int32_t num_sets, int64_t nv,
+                           int64_t N, int32_t *mem, unsigned long long *bad, hipStream_t s) {
+  HIP_TRY(hipMemsetAsync(mem, 0xff, (size_t)(N > 0 ? N : 1) * 4, s));
+  HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned long long), s));
+  int64_t work = nv > num_sets ? nv : num_sets;
+  if (work > 0)
+    hipLaunchKernelGGL(k_split_membership, dim3(nblk(work, 256)), dim3(256), 0, s, verts, set_offsets, num_sets,
+                       nv, N, mem, bad);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
+
+int front_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K, int64_t na, const int64_t *rs0,
+                      int64_t E, ItemDesc *items, int32_t *item_set, hipStream_t s) {
+  if (K > 0)
+    hipLaunchKernelGGL(k_split_items, dim3(nblk(K, 256)), dim3(256), 0, s, cl_start, cl_ids, K, na, rs0, E, items,
+                       item_set);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}

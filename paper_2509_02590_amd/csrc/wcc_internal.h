@@ -1,0 +1,45 @@
+// wcc_internal.h -- declarations shared between the translation units of the library.
+#pragma once
+
+#include "wcc_common.h"
+
+// Inputs and scratch of the front end (grouping and compaction).
+struct FrontBufs {
+  const void *off;
+  int obits;
+  const int32_t *idx;
+  const int32_t *mem;
+  int64_t N, nnz;
+  uint32_t *keys, *vals, *keys2, *vals2;   // N each
+  int32_t *flag, *flag_scan;               // N each
+  int32_t *cidv, *locv, *deg_in, *cursor;  // N each
+  void *tmp;
+  size_t tmp_bytes;
+  unsigned long long *dcnt;                // >= 8 device counters
+  int32_t *dmax;
+};
+
+// wcc_front.hip
+int front_validate(const FrontBufs &f, hipStream_t s, int *ok);
+int front_group(const FrontBufs &f, int32_t *vtx0, int64_t *cl_start, int32_t *cl_ids, int64_t *na_out,
+                int64_t *K_out, hipStream_t s);
+int front_count(const FrontBufs &f, const int32_t *vtx0, int64_t na, int32_t *rd0, int64_t *rs0,
+                int64_t *E_out, hipStream_t s);
+int front_fill(const FrontBufs &f, const int64_t *cl_start, const int64_t *rs0, int32_t *adj0, hipStream_t s);
+int front_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0, int64_t E,
+                ItemDesc *items, int32_t *nitems_dev, hipStream_t s);
+int front_split_membership(const int32_t *verts, const int64_t *set_offsets, int32_t num_sets, int64_t nv,
+                           int64_t N, int32_t *mem, unsigned long long *bad, hipStream_t s);
+int front_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K, int64_t na, const int64_t *rs0,
+                      int64_t E, ItemDesc *items, int32_t *item_set, hipStream_t s);
+
+// wcc_items.hip
+int items_block();
+int items_max_level();
+int64_t items_bitmap_words(int64_t n, int cap);
+int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s);
+int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t *set_in, int32_t *set_out,
+                    uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
+                    hipStream_t s, int max_n);
+int items_relabel(const int32_t *acc, int64_t N, int32_t *mark, int32_t *rank, int32_t *out, void *tmp,
+                  size_t tmp_bytes, hipStream_t s);

@@ -1,0 +1,204 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: bit-exact compacted
+subgraphs, cut values and sides, split records and final membership."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from graphs import complete, csr_from_edges, cycle, random_connected, random_tree
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _w():
+    import paper_2509_02590_amd as w
+    return w
+
+
+def _t(a, dtype=None):
+    a = np.ascontiguousarray(a if dtype is None else a.astype(dtype))
+    return torch.from_numpy(a).to(_dev())
+
+
+def _run(off, adj, memb, offsets32=True, **kw):
+    w = _w()
+    o = _t(off, np.int32 if offsets32 else np.int64)
+    out, st, rec = w.wcc_run(o, _t(adj, np.int32), _t(memb, np.int32), records_cap=2 * len(memb) + 16, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), st, rec
+
+
+def _rec_key(r):
+    return sorted(tuple(int(x) for x in (q["minv"], q["n"], q["k"], q["lam"], q["ssize"], q["shash"])) for q in r)
+
+
+def _compare(off, adj, memb, s_pre=10, s_post=10, mode="kcore", offsets32=True, criterion="log10"):
+    want, wrec = oracle.wcc(off, adj, memb, s_pre=s_pre, s_post=s_post, mode=mode, criterion=criterion)
+    got, st, grec = _run(off, adj, memb, offsets32=offsets32, s_pre=s_pre, s_post=s_post, mode=mode,
+                         criterion=criterion)
+    assert np.array_equal(got, want), "membership differs (%d of %d)" % ((got != want).sum(), len(want))
+    assert _rec_key(grec) == _rec_key(wrec)
+    return st
+
+
+# ------------------------------------------------------------------ compaction
+@pytest.mark.parametrize("which", ["tiny", "chunglu_small"])
+def test_cluster_csr_matches_oracle(which):
+    g = gen.c0() if which == "tiny" else gen.chung_lu(30000, 30.0, 2.5, 11, 800, 2.0, 0.2, 0.15, 0.05, seed=9)
+    memb = g.membership.copy()
+    memb[::17] = -1                                  # some unassigned vertices
+    memb = np.where(memb >= 0, memb * 7 + 3, memb)   # non-dense cluster ids
+    want = oracle.cluster_csr(g.offsets, g.indices, memb)
+    w = _w()
+    got = w.cluster_csr(_t(g.offsets), _t(g.indices), _t(memb, np.int32))
+    got = {k: v.cpu().numpy() for k, v in got.items()}
+    for k in ("cl_ids", "cl_start", "vert", "row_off"):
+        assert np.array_equal(got[k], want[k]), k
+    ro = want["row_off"]
+    ga = got["adj"].copy()
+    for i in range(len(ro) - 1):
+        ga[ro[i]:ro[i + 1]].sort()                   # row order is unspecified
+    assert np.array_equal(ga, want["adj"])
+
+
+# ------------------------------------------------------------------ min cut
+def _pack(graphs):
+    """Disjoint union of (n, edges) graphs -> CSR, verts, set offsets."""
+    edges, base, so = [], 0, [0]
+    for n, e in graphs:
+        edges += [(a + base, b + base) for a, b in e]
+        base += n
+        so.append(base)
+    off, adj = csr_from_edges(base, edges)
+    return off, adj, np.arange(base, dtype=np.int32), np.array(so, np.int64)
+
+
+def test_mincut_split_batch_random_small():
+    rng = np.random.default_rng(4242)
+    graphs = []
+    for i in range(600):
+        n = int(rng.integers(2, 40))
+        p = float(rng.choice([0.08, 0.2, 0.5, 0.9]))
+        graphs.append((n, random_connected(rng, n, p)))
+    graphs += [(12, complete(12)), (30, cycle(30)), (25, random_tree(rng, 25)), (1, []), (2, [])]
+    off, adj, verts, so = _pack(graphs)
+    caps = rng.integers(1, 8, len(graphs)).astype(np.int32)
+    caps[::5] = 2**31 - 1
+    caps[-6:] = [3, 2**31 - 1, 2, 2, 2, 2]
+    w = _w()
+    lam, side = w.mincut_split_batch(_t(off, np.int32), _t(adj), _t(verts), _t(so), _t(caps))
+    lam, side = lam.cpu().numpy(), side.cpu().numpy().astype(bool)
+    for i, (n, e) in enumerate(graphs):
+        wl, ws = oracle.mincut_split(off, adj, verts[so[i]:so[i + 1]], int(caps[i]))
+        assert lam[i] == wl, (i, n)
+        assert np.array_equal(side[so[i]:so[i + 1]], ws), (i, n)
+
+
+def test_mincut_split_single_and_disconnected():
+    w = _w()
+    e = complete(6) + [(a + 6, b + 6) for a, b in complete(5)]
+    off, adj = csr_from_edges(11, e)
+    lam, side = w.mincut_split(_t(off), _t(adj), _t(np.arange(11), np.int32), 3)
+    assert lam == 0 and side.cpu().numpy().astype(bool).tolist() == [True] * 6 + [False] * 5
+    lam, side = w.mincut_split(_t(off), _t(adj), _t(np.arange(6, 11), np.int32), 2**31 - 1)
+    assert lam == 4 and side.cpu().numpy().tolist() == [1, 0, 0, 0, 0]
+
+
+# ------------------------------------------------------------------ whole WCC
+@pytest.mark.parametrize("mode", ["kcore", "paper"])
+def test_wcc_tiny_workload(mode):
+    g = gen.c0()
+    st = _compare(g.offsets, g.indices, g.membership, mode=mode)
+    assert st.accepted > 0
+
+
+@pytest.mark.parametrize("mode", ["kcore", "paper"])
+def test_wcc_random_clustered(mode):
+    rng = np.random.default_rng(55 if mode == "kcore" else 56)
+    for trial in range(12):
+        n = int(rng.integers(50, 400))
+        nclust = int(rng.integers(1, 8))
+        memb = rng.integers(-1, nclust, n).astype(np.int32)
+        edges = set()
+        for a in range(n):
+            for b in range(a + 1, n):
+                same = memb[a] == memb[b] and memb[a] >= 0
+                if rng.random() < (float(rng.choice([0.1, 0.3])) if same else 0.01):
+                    edges.add((a, b))
+        off, adj = csr_from_edges(n, sorted(edges))
+        for s in (1, 5, 10):
+            _compare(off, adj, memb, s_pre=s, s_post=s, mode=mode)
+
+
+def test_wcc_special_cases():
+    # two K11 joined by a bridge; K_n; tree; disjoint union; cycle with a pendant
+    e = complete(11) + complete(11, 11) + [(10, 11)]
+    off, adj = csr_from_edges(22, e)
+    for s in (10, 11):
+        for mode in ("kcore", "paper"):
+            _compare(off, adj, np.zeros(22, np.int32), s_pre=s, s_post=s, mode=mode)
+    e = cycle(99) + [(98, 99)]
+    off, adj = csr_from_edges(100, e)
+    for mode in ("kcore", "paper"):
+        _compare(off, adj, np.zeros(100, np.int32), mode=mode)
+    rng = np.random.default_rng(2)
+    off, adj = csr_from_edges(60, random_tree(rng, 60))
+    _compare(off, adj, np.zeros(60, np.int32), mode="paper")
+
+
+def test_wcc_edge_cases():
+    w = _w()
+    # empty graph
+    out, st, _ = _run(np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert out.shape == (0,)
+    # no edges at all
+    memb = np.zeros(50, np.int32)
+    got, _, _ = _run(np.zeros(51, np.int64), np.zeros(0, np.int32), memb)
+    assert np.all(got == -1)
+    # everything unassigned
+    off, adj = csr_from_edges(30, complete(30))
+    got, _, _ = _run(off, adj, np.full(30, -1, np.int32))
+    assert np.all(got == -1)
+    # large cluster ids and 64-bit offsets
+    memb = np.full(30, 2**31 - 2, np.int32)
+    _compare(off, adj, memb, offsets32=False)
+    # invalid parameters are rejected
+    with pytest.raises(w.WccError):
+        _run(off, adj, memb, s_post=-1)
+
+
+def test_wcc_validate_flag():
+    w = _w()
+    off, adj = csr_from_edges(20, complete(20))
+    memb = np.zeros(20, np.int32)
+    _run(off, adj, memb, validate=True)
+    bad = adj.copy()
+    bad[0] = 0  # self-loop on vertex 0
+    with pytest.raises(w.WccError) as ei:
+        _run(off, bad, memb, validate=True)
+    assert ei.value.code == -2
+    bad = adj.copy()
+    bad[5] = (bad[5] + 1) % 20 if bad[5] != 19 else 18   # asymmetric entry
+    with pytest.raises(w.WccError):
+        _run(off, bad, memb, validate=True)
+
+
+@pytest.mark.parametrize("mode", ["kcore", "paper"])
+def test_wcc_chunglu_medium(mode):
+    g = gen.chung_lu(60000, 30.0, 2.5, 11, 2000, 2.0, 0.2, 0.15, 0.05, seed=77, intra_mult=1.8)
+    _compare(g.offsets, g.indices, g.membership, mode=mode)
+
+
+def test_wcc_c1_full_kcore():
+    """The 1M-vertex / 20M-edge workload in the benchmark's launch configuration."""
+    g = gen.c1()
+    st = _compare(g.offsets, g.indices, g.membership, mode="kcore")
+    assert st.mincuts > 1000
