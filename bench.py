@@ -1,0 +1,145 @@
+"""Benchmark of the WCC hot path on one MI355X.
+
+A step is one whole wcc_run (front end, CCR, pruning, every minimum cut and split, and the
+final relabel) over the 1M-vertex / 20M-edge Chung-Lu workload with a planted power-law
+clustering (input already resident in HBM).  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2]
+                  [--exec plain|batched] [--mode kcore|paper] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WCC input edges processed/s (batched vs plain GPU), HBM GB/s; p50/p99 job ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import gen
+    if name == "c0":
+        return gen.c0()
+    if name == "c1":
+        return gen.c1()
+    if name == "c2":
+        return gen.c2()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(g, mode, threads):
+    """The oracle, as it stands, on the same workload (one full run)."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.wcc(g, s_pre=10, s_post=10, mode=mode, nthreads=threads, log=False)
+    dt = time.perf_counter() - t0
+    return {"value": g.m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": "one full run of the same %s workload (%d edges), %.2f s" % (g.meta["workload"], g.m, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--exec", dest="exec_mode", default="plain")
+    ap.add_argument("--mode", default="kcore")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-bytes", type=float, default=None,
+                    help="HBM bytes per item launch measured by rocprofv3 counters (optional)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2509_02590_amd as wcc
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    g = workload(args.workload)
+    log("workload %s: n=%d m=%d clusters=%d mixing=%.3f (generated in %.1f s)"
+        % (g.meta["workload"], g.n, g.m, g.meta["clusters"], g.meta["mixing"], time.perf_counter() - t0))
+    obits = np.int32 if g.indices.shape[0] < 2**31 else np.int64
+    off = torch.from_numpy(g.offsets.astype(obits)).to(dev)
+    idx = torch.from_numpy(g.indices).to(dev)
+    mem = torch.from_numpy(g.membership).to(dev)
+    out = torch.empty_like(mem)
+    kw = dict(s_pre=10, s_post=10, mode=args.mode, exec_mode=args.exec_mode)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        wcc.wcc_run(off, idx, mem, out=out, **kw)
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    stats = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        _, st, _ = wcc.wcc_run(off, idx, mem, out=out, **kw)
+        stats.append(st.as_dict())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_step = 1000.0 * elapsed / args.steps
+    value = g.m / (elapsed / args.steps)
+    log("timed %d steps: %.2f ms/step, %.3e edges/s" % (args.steps, ms_step, value))
+
+    # roofline of the dominant kernel (the per-item kernel), timed with HIP events that
+    # the library records around every item launch on the caller's stream
+    s0 = stats[-1]
+    launches = max(s0["item_launches"], 1)
+    avg_launch_s = s0["ms_item_kernel"] / 1000.0 / launches
+    alg_bytes_per_launch = s0["item_alg_bytes"] / launches
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    traffic = args.traffic_bytes
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_items", "avg_launch_ms": avg_launch_s * 1e3,
+                "alg_bytes_per_launch": alg_bytes_per_launch, "launches_per_step": s0["item_launches"]}
+
+    # whole-job floor: one pass over the input (SURVEY-style B_floor), for context
+    b_floor = g.indices.shape[0] * 8 + g.n * (4 + 4 + 4)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": g.meta["workload"], "vertices": g.n, "edges": g.m,
+                   "clusters": g.meta["clusters"], "mixing": round(g.meta["mixing"], 4),
+                   "exec": args.exec_mode, "prune": args.mode, "criterion": "log10",
+                   "s_pre": 10, "s_post": 10},
+        "roofline": roofline,
+        "floor_gbs": b_floor / (elapsed / args.steps) / 1e9,
+        "step_stats": {k: s0[k] for k in ("items", "mincuts", "accepted", "levels", "scan_steps",
+                                           "scan_rounds", "ms_front", "ms_items", "ms_item_kernel")},
+    }
+    if not args.no_cpu_baseline:
+        try:
+            threads = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            threads = min(16, os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline(g, args.mode, threads)
+        log("cpu baseline: %.3e edges/s on %d threads" % (line["cpu_baseline"]["value"], threads))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

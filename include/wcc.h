@@ -117,6 +117,9 @@ typedef struct {
   double ms_item_kernel; /* summed durations of the item-kernel launches */
   int64_t item_launches; /* number of item-kernel launches */
   double ms_total;       /* host wall time of the call */
+  int64_t item_alg_bytes; /* algorithmic bytes of the item launches: each processed set's
+                             rows read once (16 B per vertex + 4 B per entry), each child's
+                             rows written once, 4 B per saved vertex */
 } wcc_stats;
 
 /* One record per minimum-cut evaluation (order of records is unspecified). */

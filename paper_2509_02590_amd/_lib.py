@@ -58,7 +58,7 @@ class Stats(ctypes.Structure):
                 ("scan_steps", ctypes.c_int64), ("scan_rounds", ctypes.c_int64),
                 ("ms_front", ctypes.c_double), ("ms_items", ctypes.c_double),
                 ("ms_item_kernel", ctypes.c_double), ("item_launches", ctypes.c_int64),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("item_alg_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -49,7 +49,7 @@ enum BufId {
   B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_LOCV, B_DEGIN, B_CURSOR,
   B_ACC, B_MARK, B_RANK, B_TMP, B_DCNT, B_CLSTART, B_CLIDS,
   B_VTX0, B_VTX1, B_RS0, B_RS1, B_RD0, B_RD1, B_ADJ0, B_ADJ1,
-  B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SEDGE, B_GBITS,
+  B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SG, B_SEDGE, B_SMARK, B_GBITS,
   B_ITEMS0, B_ITEMS1, B_ITEMS_SORTED, B_SET0, B_SET_SORTED, B_IKEYS, B_IVALS, B_IKEYS2, B_IVALS2,
   B_SPLITMEM, B_SMALL,
   B_NUM
@@ -57,7 +57,8 @@ enum BufId {
 
 struct Workspace {
   Buf b[B_NUM];
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evj = nullptr;
+  hipStream_t s2 = nullptr;  // second stream (default priority) for the large-item launch
   int cus = 0;
   void release() {
     for (auto &x : b) x.release();
@@ -78,6 +79,8 @@ int get_ws(Workspace **out) {
     w->cus = prop.multiProcessorCount;
     HIP_TRY(hipEventCreate(&w->ev0));
     HIP_TRY(hipEventCreate(&w->ev1));
+    HIP_TRY(hipEventCreateWithFlags(&w->evj, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&w->s2, hipStreamNonBlocking));
     g_ws[dev] = w;
   }
   *out = g_ws[dev];
@@ -128,7 +131,8 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
   int64_t N = g->num_vertices;
   size_t n4 = (size_t)(N > 0 ? N : 1) * 4;
   for (int id : {B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_LOCV, B_DEGIN, B_CURSOR,
-                 B_ACC, B_MARK, B_RANK, B_VTX0, B_VTX1, B_RD0, B_RD1, B_SA, B_SB, B_SC, B_SD, B_SE, B_SF})
+                 B_ACC, B_MARK, B_RANK, B_VTX0, B_VTX1, B_RD0, B_RD1, B_SA, B_SB, B_SC, B_SD, B_SE, B_SF,
+                 B_SG})
     TRY(w.b[id].ensure(n4));
   TRY(w.b[B_RS0].ensure(2 * n4 + 8));
   TRY(w.b[B_RS1].ensure(2 * n4 + 8));
@@ -137,7 +141,7 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
   size_t tmpb = prim_radix_tmp_bytes(N > 0 ? N : 1);
   size_t sb = prim_scan_tmp_bytes(N > 0 ? N : 1);
   TRY(w.b[B_TMP].ensure(tmpb > sb ? tmpb : sb));
-  TRY(w.b[B_DCNT].ensure(64 * sizeof(unsigned long long)));
+  TRY(w.b[B_DCNT].ensure(128 * sizeof(unsigned long long)));
 
   FrontBufs f;
   f.off = g->row_offsets;
@@ -173,6 +177,7 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
   TRY(w.b[B_ADJ0].ensure(e4));
   TRY(w.b[B_ADJ1].ensure(e4));
   TRY(w.b[B_SEDGE].ensure(e4));
+  TRY(w.b[B_SMARK].ensure(e4 / 4 + 64));
   TRY(front_fill(f, w.b[B_CLSTART].as<int64_t>(), w.b[B_RS0].as<int64_t>(), w.b[B_ADJ0].as<int32_t>(), s));
   return WCC_OK;
 }
@@ -181,13 +186,30 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Processes item lists level by level until no children remain.
+// Largest n whose item state fits `words` 32-bit LDS words (cap from the criterion).
+int small_max_n(int64_t words, int crit, const wcc_params &p, bool split) {
+  int64_t lo = 0, hi = 1 << 24;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) / 2;
+    int cap = split ? items_max_level() : (int)wcc_k_of(crit, mid, p.lin_num, p.lin_den);
+    if (items_lds_words(mid, cap) <= words) lo = mid;
+    else hi = mid - 1;
+  }
+  return (int)lo;
+}
+
+// Processes item lists level by level until no children remain.  Each level is sorted
+// by size (largest first) and split into two launches that run concurrently: the items
+// whose state does not fit the small LDS budget go to a workgroup per CU with the full
+// 160 KB of LDS on a second stream, the rest to many small-LDS workgroups.
 int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, const wcc_params &p,
                int64_t *levels, double *ms_kernel, int64_t *launches, hipStream_t s) {
   int lds_kb = env_int("WCC_LDS_KB", 32);
   if (lds_kb < 4) lds_kb = 4;
-  if (lds_kb > 160) lds_kb = 160;
+  if (lds_kb > 64) lds_kb = 64;
   size_t lds_bytes = (size_t)lds_kb * 1024;
+  size_t big_bytes = (size_t)env_int("WCC_BIG_LDS_KB", 159) * 1024;
+  if (big_bytes > 159 * 1024) big_bytes = 159 * 1024;
   int per_cu = env_int("WCC_WG_PER_CU", 0);
   if (per_cu <= 0) per_cu = (int)(160 / lds_kb) > 8 ? 8 : (int)(160 / lds_kb);
   if (per_cu < 1) per_cu = 1;
@@ -196,9 +218,12 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
   int cur = 0;  // items in B_ITEMS0 (cur==0) or B_ITEMS1
   int32_t *dcount = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16);
   int32_t *dnext = dcount + 1;
+  int32_t *dnext_big = dcount + 2;
+  int32_t *dnbig = dcount + 3;
   ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
   int32_t *set_sorted = base.split_only ? w.b[B_SET_SORTED].as<int32_t>() : nullptr;
   const int32_t *set_in = base.split_only ? w.b[B_SET0].as<int32_t>() : nullptr;
+  int small_max = small_max_n((int64_t)(lds_bytes / 4), max_cap_crit, p, base.split_only);
   *levels = 0;
   *ms_kernel = 0;
   *launches = 0;
@@ -207,28 +232,47 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     ItemDesc *out = w.b[cur ? B_ITEMS0 : B_ITEMS1].as<ItemDesc>();
     TRY(items_sort_desc(in, nitems, sorted, set_in, set_sorted, w.b[B_IKEYS].as<uint32_t>(),
                         w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(), w.b[B_IVALS2].as<uint32_t>(),
-                        w.b[B_TMP].p, w.b[B_TMP].bytes, s, 0));
+                        w.b[B_TMP].p, w.b[B_TMP].bytes, s, small_max, dnbig));
     ItemDesc top;
+    int32_t nbig = 0;
     HIP_TRY(hipMemcpyAsync(&top, sorted, sizeof(top), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&nbig, dnbig, sizeof(nbig), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int grid = nitems < gmax ? nitems : gmax;
+    int32_t nsmall = nitems - nbig;
+    int grid_small = nsmall < gmax ? nsmall : gmax;
+    int grid_big = nbig < w.cus ? nbig : w.cus;
     int cap_top = base.split_only ? items_max_level()
                                   : (int)wcc_k_of(max_cap_crit, top.n, p.lin_num, p.lin_den);
     int64_t words = items_bitmap_words(top.n, cap_top);
-    TRY(w.b[B_GBITS].ensure((size_t)grid * words * 8 + 64));
+    TRY(w.b[B_GBITS].ensure((size_t)(grid_big > 0 ? grid_big : 1) * words * 8 + 64));
     ItemArgs A = base;
     A.gbits = w.b[B_GBITS].as<uint64_t>();
     A.gbits_words = words;
-    A.items = sorted;
-    A.nitems = nitems;
-    A.next = dnext;
     A.out = out;
     A.out_count = dcount;
-    A.lds_words = (int32_t)(lds_bytes / 4);
     if (base.split_only) A.split_set = set_sorted;
-    HIP_TRY(hipMemsetAsync(dcount, 0, 2 * sizeof(int32_t), s));
+    HIP_TRY(hipMemsetAsync(dcount, 0, 3 * sizeof(int32_t), s));
     HIP_TRY(hipEventRecord(w.ev0, s));
-    TRY(items_launch(A, grid, lds_bytes, s));
+    if (nbig > 0) {
+      ItemArgs Bg = A;
+      Bg.items = sorted;
+      Bg.nitems = nbig;
+      Bg.next = dnext_big;
+      Bg.lds_words = (int32_t)(big_bytes / 4);
+      HIP_TRY(hipStreamWaitEvent(w.s2, w.ev0, 0));
+      TRY(items_launch(Bg, grid_big, big_bytes, w.s2));
+      HIP_TRY(hipEventRecord(w.evj, w.s2));
+    }
+    if (nsmall > 0) {
+      ItemArgs Sm = A;
+      Sm.items = sorted + nbig;
+      Sm.nitems = nsmall;
+      Sm.next = dnext;
+      Sm.lds_words = (int32_t)(lds_bytes / 4);
+      if (base.split_only) Sm.split_set = set_sorted + nbig;
+      TRY(items_launch(Sm, grid_small, lds_bytes, s));
+    }
+    if (nbig > 0) HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
     HIP_TRY(hipEventRecord(w.ev1, s));
     int32_t nout = 0;
     HIP_TRY(hipMemcpyAsync(&nout, dcount, sizeof(nout), hipMemcpyDeviceToHost, s));
@@ -267,6 +311,8 @@ ItemArgs base_args(Workspace &w, const wcc_params &p, int32_t item_cap) {
   A.sD = w.b[B_SD].as<int32_t>();
   A.sE = w.b[B_SE].as<int32_t>();
   A.sF = w.b[B_SF].as<int32_t>();
+  A.sG = w.b[B_SG].as<int32_t>();
+  A.sMark = w.b[B_SMARK].as<uint8_t>();
   A.sEdge = w.b[B_SEDGE].as<int32_t>();
   A.acc = w.b[B_ACC].as<int32_t>();
   A.out_cap = item_cap;
@@ -338,6 +384,7 @@ int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, 
   ItemArgs A = base_args(w, p, (int32_t)(fo.na + 1));
   A.rec = rec;
   A.rec_cap = rec_cap;
+  A.prof = env_int("WCC_PROF", 0);
   auto t1 = std::chrono::steady_clock::now();
   TRY(run_levels(w, A, nitems, p.criterion, p, &st.levels, &st.ms_item_kernel, &st.item_launches, s));
   TRY(items_relabel(w.b[B_ACC].as<int32_t>(), N, w.b[B_MARK].as<int32_t>(), w.b[B_RANK].as<int32_t>(), out,
@@ -351,6 +398,16 @@ int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, 
   st.accepted = (int64_t)hc[CNT_ACCEPTED];
   st.scan_steps = (int64_t)hc[CNT_STEPS];
   st.scan_rounds = (int64_t)hc[CNT_ROUNDS];
+  st.item_alg_bytes = (int64_t)hc[CNT_ALG_BYTES];
+  if (A.prof) {
+    static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
+                                  "lists", "degree", "record", "split-rebuild", "", "", "scanned-entries"};
+    fprintf(stderr, "[wcc phase ms, summed over workgroups]");
+    for (int i = 0; i < 13; i++)
+      if (names[i][0])
+        fprintf(stderr, " %s=%.2f", names[i], i == 12 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
+    fprintf(stderr, "\n");
+  }
   if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
   st.ms_total = ms_since(t0);
   if (stats) *stats = st;
@@ -368,7 +425,7 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   Workspace &w = *wp;
   int64_t N = g->num_vertices;
   TRY(w.b[B_SPLITMEM].ensure((size_t)(N > 0 ? N : 1) * 4));
-  TRY(w.b[B_DCNT].ensure(64 * sizeof(unsigned long long)));
+  TRY(w.b[B_DCNT].ensure(128 * sizeof(unsigned long long)));
   HIP_TRY(hipMemsetAsync(lambdas, 0, (size_t)num_sets * 4, s));
   if (nv > 0) HIP_TRY(hipMemsetAsync(sides, 0, (size_t)nv, s));
   if (nv == 0) {
@@ -377,7 +434,7 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   }
   if (!verts || !sides) return WCC_EINVAL;
   int32_t *mem = w.b[B_SPLITMEM].as<int32_t>();
-  unsigned long long *bad = w.b[B_DCNT].as<unsigned long long>() + 48;
+  unsigned long long *bad = w.b[B_DCNT].as<unsigned long long>() + 100;
   TRY(front_split_membership(verts, set_offsets, num_sets, nv, N, mem, bad, s));
   unsigned long long hb = 0;
   HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));

@@ -84,13 +84,18 @@ enum : int32_t {
   CNT_ROUNDS,
   CNT_RECORDS,
   CNT_ERR,  // first error code seen by a kernel (atomicMin of negative codes)
+  CNT_ALG_BYTES,  // algorithmic bytes of the item launches (reads + writes)
+  CNT_PH,         // 16 slots: optional per-phase clock totals (profiling builds of a run)
+  CNT_PH_END = CNT_PH + 16,
   CNT_NUM
 };
 
 struct ItemArgs {
   Arena ar[2];
   int32_t *sA, *sB, *sC, *sD, *sE, *sF;  // per-position scratch
-  int32_t *sEdge;                   // per-entry scratch
+  int32_t *sG;                      // per-position scratch (row starts of global-state items)
+  int32_t *sEdge;                   // per-entry scratch (crossing lists)
+  uint8_t *sMark;                   // per-entry scratch (contraction marks)
   uint64_t *gbits;                  // per-workgroup bitmap regions (large items)
   int64_t gbits_words;              // words per workgroup region
   int32_t *acc;                     // N: smallest global id of the saved set, or -1
@@ -105,6 +110,7 @@ struct ItemArgs {
   wcc_record *rec;
   int64_t rec_cap;
   unsigned long long *cnt;          // CNT_* counters
+  int32_t prof;                     // accumulate per-phase clock totals into CNT_PH slots
   int32_t split_only;               // mincut_split mode: items are caller sets
   int32_t *split_lambda;            // per set (mincut_split mode)
   uint8_t *split_side;              // per position (mincut_split mode)

@@ -107,6 +107,7 @@ __global__ void k_member_stats(const int32_t *mem, int64_t N, int32_t *maxid, un
     m = mem[i];
     c = m >= 0;
   }
+  __shared__ int ws[16], wm[16];
   int s = wave_sum(c);
   int32_t mx = m;
 #pragma unroll
@@ -115,8 +116,18 @@ __global__ void k_member_stats(const int32_t *mem, int64_t N, int32_t *maxid, un
     mx = t > mx ? t : mx;
   }
   if (__lane_id() == 0) {
-    if (s) atomicAdd(na, (unsigned long long)s);
-    if (mx >= 0) atomicMax(maxid, mx);
+    ws[threadIdx.x >> 6] = s;
+    wm[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one pair of atomics per block
+    int ts = 0, tm = -1;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+      ts += ws[w];
+      tm = wm[w] > tm ? wm[w] : tm;
+    }
+    if (ts) atomicAdd(na, (unsigned long long)ts);
+    if (tm >= 0) atomicMax(maxid, tm);
   }
 }
 
@@ -201,7 +212,9 @@ __global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t
   rs0[p] = d;
 }
 
-// adj0[rs0[pos(v)] + slot] = local id of each intra neighbour; slots from a per-row cursor
+// adj0[rs0[pos(v)] + slot] = local id of each intra neighbour.  Slots come from a per-row
+// cursor; inside a tile the row's intra entries are counted in LDS first, so each
+// (row, tile) pair reserves its slots with one global atomic.
 template <typename OT>
 __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t *idx, int64_t N,
                                                    int64_t nnz, const int32_t *cidv,
@@ -210,21 +223,56 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
                                                    int32_t *adj0) {
   __shared__ int64_t sh_r[2];
   __shared__ int64_t cache[FROWS];
+  __shared__ int cnt[FROWS];
   int64_t e0 = (int64_t)blockIdx.x * FTILE, e1 = e0 + FTILE < nnz ? e0 + FTILE : nnz;
   bool cached = tile_rows(off, N, e0, e1, sh_r, cache);
   int64_t r0 = sh_r[0], r1 = sh_r[1];
+  if (!cached) {
+    for (int i = 0; i < FITEMS; i++) {
+      int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
+      if (e >= e1) break;
+      int64_t v = row_of(off, r0, r1, e);
+      int32_t cv = cidv[v];
+      if (cv < 0) continue;
+      int32_t u = idx[e];
+      if (cidv[u] != cv) continue;
+      int64_t pv = cl_start[cv] + locv[v];
+      int32_t slot = atomicAdd(&cursor[v], 1);
+      adj0[rs0[pv] + slot] = locv[u];
+    }
+    return;
+  }
+  int nr = (int)(r1 - r0 + 1);
+  for (int i = threadIdx.x; i < nr; i += FB) cnt[i] = 0;
+  __syncthreads();
+  int val[FITEMS], slot[FITEMS], row[FITEMS];
+#pragma unroll
   for (int i = 0; i < FITEMS; i++) {
+    val[i] = -1;
     int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
-    if (e >= e1) break;
-    int64_t v = cached ? r0 + row_in_cache(cache, r1 - r0 + 2, e) : row_of(off, r0, r1, e);
-    int32_t cv = cidv[v];
+    if (e >= e1) continue;
+    int r = (int)row_in_cache(cache, nr + 1, e);
+    row[i] = r;
+    int32_t cv = cidv[r0 + r];
     if (cv < 0) continue;
     int32_t u = idx[e];
     if (cidv[u] != cv) continue;
-    int64_t pv = cl_start[cv] + locv[v];
-    int32_t slot = atomicAdd(&cursor[v], 1);
-    adj0[rs0[pv] + slot] = locv[u];
+    val[i] = locv[u];
+    slot[i] = atomicAdd(&cnt[r], 1);
   }
+  __syncthreads();
+  // one reservation per row of the tile; cache[] is reused for the row's write base
+  for (int r = threadIdx.x; r < nr; r += FB) {
+    int c = cnt[r];
+    if (c == 0) continue;
+    int64_t v = r0 + r;
+    int64_t pv = cl_start[cidv[v]] + locv[v];
+    cache[r] = rs0[pv] + atomicAdd(&cursor[v], c);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < FITEMS; i++)
+    if (val[i] >= 0) adj0[cache[row[i]] + slot[i]] = val[i];
 }
 
 __global__ void k_make_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0,
@@ -292,7 +340,7 @@ int front_group(const FrontBufs &f, int32_t *vtx0, int64_t *cl_start, int32_t *c
   int64_t N = f.N;
   HIP_TRY(hipMemsetAsync(f.dcnt, 0, sizeof(unsigned long long), s));
   HIP_TRY(hipMemsetAsync(f.dmax, 0xff, sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_member_stats, dim3(nblk(N, 256)), dim3(256), 0, s, f.mem, N, f.dmax, f.dcnt);
+  hipLaunchKernelGGL(k_member_stats, dim3(nblk(N, 1024)), dim3(1024), 0, s, f.mem, N, f.dmax, f.dcnt);
   HIP_TRY(hipGetLastError());
   unsigned long long na = 0;
   int32_t maxid = -1;

@@ -35,11 +35,12 @@ int front_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K,
 
 // wcc_items.hip
 int items_block();
+int64_t items_lds_words(int64_t n, int cap);
 int items_max_level();
 int64_t items_bitmap_words(int64_t n, int cap);
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s);
 int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t *set_in, int32_t *set_out,
                     uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
-                    hipStream_t s, int max_n);
+                    hipStream_t s, int small_max, int32_t *nbig);
 int items_relabel(const int32_t *acc, int64_t N, int32_t *mark, int32_t *rank, int32_t *out, void *tmp,
                   size_t tmp_bytes, hipStream_t s);

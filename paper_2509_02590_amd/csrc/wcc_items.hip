@@ -9,14 +9,25 @@
 //   * acceptance (cut > f(n), i.e. cut >= k(n)) or a split into the cut's two sides,
 //     each rebuilt as a compacted induced subgraph in the other arena (Alg. 3).
 //
-// Per-item state lives in LDS when it fits the launch's dynamic LDS, else in the global
-// per-position scratch slices [b, b+n) (items of one launch are disjoint) plus a
-// per-workgroup bitmap region; the code reaches both through generic pointers.
+// Placement.  The arrays the scan touches every step (keys A, union-find B, list lengths
+// D and starts E, row starts R and the level bitmaps) live in LDS when they fit the
+// launch's LDS budget, otherwise in global scratch; the item's own adjacency is also
+// copied to LDS as 16-bit ids when it fits too.  Super-vertex ids C, the cut side F and
+// the per-entry contraction marks always live in global scratch.  Items of one launch
+// are disjoint, so position- and entry-indexed scratch slices never overlap.
 //
-// The maximum-adjacency scan keeps, for every key level j in 0..bound, a 3-level bitmap
-// of the unscanned super-vertices whose key is >= j (level 0 = all unscanned).  The next
-// vertex is the smallest id in the highest non-empty level, found in four dependent
-// reads; a key increment only ever sets one bit, so concurrent updates commute.
+// The maximum-adjacency scan is run by one wavefront.  For every key level j in 0..bound
+// a hierarchical bitmap holds the unscanned super-vertices whose key is >= j (level 0 =
+// all unscanned); the next vertex is the smallest id of the highest non-empty level.  A
+// key increment sets exactly one bit, so concurrent increments commute; contractible
+// edges are only marked during the scan (a store nobody waits for) and merged with a
+// union-find pass afterwards.  When the neighbour lists are in global memory the list
+// of the likely next vertex is prefetched into registers while the current one is
+// processed.
+//
+// Passes over all edges of an item are entry-parallel: each thread takes 16 consecutive
+// entries (coalesced loads) and finds their owners by a binary search in the LDS copy
+// of the row starts.
 #include "wcc_internal.h"
 
 namespace {
@@ -24,6 +35,7 @@ namespace {
 constexpr int IB = 256;  // threads per item workgroup
 constexpr int NW = IB / 64;
 constexpr int MAX_LEVEL = 62;
+constexpr int CH = 16;   // entries per thread per chunk in entry-parallel passes
 
 struct Sh {
   int red[NW + 1];
@@ -35,11 +47,19 @@ struct Sh {
 };
 
 struct St {
-  int32_t *A, *B, *C, *D, *E, *F;  // n each
-  uint64_t *bits;              // bitmap area
-  int n;
+  int32_t *A, *B, *D, *E, *R;  // LDS or global
+  int32_t *C, *F;              // global
+  uint64_t *bits;              // LDS or global
+  uint16_t *adj16;             // LDS copy of the item's adjacency, or nullptr
+  const int32_t *adjg;         // the item's adjacency in the arena (entry 0 = eb)
+  uint8_t *mark;               // global, entry-indexed contraction marks
+  int32_t *lists;              // global, entry-indexed crossing lists (rounds >= 2)
+  int n, m;
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
 };
+
+DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ld(&s.R[x + 1]) : s.m; }
+DEV int adj_at(const St &s, int e) { return s.adj16 ? (int)s.adj16[e] : s.adjg[e]; }
 
 DEV int uf_find(int32_t *P, int x) {
   for (;;) {
@@ -67,6 +87,37 @@ DEV void uf_unite(int32_t *P, int a, int b) {
   }
 }
 
+// Calls f(x, e, y) for every entry e in [0, total) of lists stored in ascending owner
+// order: owner x covers [start[x], end(x)), end(x) = start[x+1] (or total for the last),
+// and y = get(e).  Each thread takes CH consecutive entries.
+template <typename G, typename F>
+DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
+  for (int base = threadIdx.x * CH; base < total; base += IB * CH) {
+    int yv[CH];
+#pragma unroll
+    for (int i = 0; i < CH; i++) yv[i] = base + i < total ? get(base + i) : 0;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (ld(&start[mid]) <= base) lo = mid;
+      else hi = mid - 1;
+    }
+    int x = lo;
+    int xend = x + 1 < n ? ld(&start[x + 1]) : total;
+#pragma unroll
+    for (int i = 0; i < CH; i++) {
+      int e = base + i;
+      if (e < total) {
+        while (e >= xend) {
+          x++;
+          xend = x + 1 < n ? ld(&start[x + 1]) : total;
+        }
+        f(x, e, yv[i]);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- bitmap levels
 DEV uint64_t *lvl0(const St &s, int j) { return s.bits + (size_t)j * s.ls; }
 DEV uint64_t *lvl1(const St &s, int j) { return s.bits + (size_t)j * s.ls + s.nw0; }
@@ -76,7 +127,7 @@ DEV void bit_set(const St &s, int j, int y, unsigned long long *levelmask) {
   unsigned long long old = atomicOr((unsigned long long *)&lvl0(s, j)[y >> 6], 1ull << (y & 63));
   if (old) return;
   old = atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
-  if (old) return;
+  if (old || s.nw1 == 1) return;
   old = atomicOr((unsigned long long *)&lvl2(s, j)[y >> 18], 1ull << ((y >> 12) & 63));
   if (old) return;
   atomicOr(levelmask, 1ull << j);
@@ -88,7 +139,7 @@ DEV void bit_clear(const St &s, int j, int x, unsigned long long *levelmask) {
   if (old != b) return;
   b = 1ull << ((x >> 6) & 63);
   old = atomicAnd((unsigned long long *)&lvl1(s, j)[x >> 12], ~b);
-  if (old != b) return;
+  if (old != b || s.nw1 == 1) return;
   b = 1ull << ((x >> 12) & 63);
   old = atomicAnd((unsigned long long *)&lvl2(s, j)[x >> 18], ~b);
   if (old != b) return;
@@ -99,29 +150,62 @@ DEV void bit_clear(const St &s, int j, int x, unsigned long long *levelmask) {
 
 DEV bool bit_test(const St &s, int j, int y) { return (ld(&lvl0(s, j)[y >> 6]) >> (y & 63)) & 1ull; }
 
-// smallest id in the highest non-empty level, or -1
-DEV int bit_pick(const St &s, unsigned long long lm) {
-  if (!lm) return -1;
-  int j = 63 - __clzll(lm);
-  const uint64_t *L2 = lvl2(s, j);
-  uint64_t w = 0;
-  int t = 0;
-  for (; t < s.nw2; t++) {
-    w = ld(&L2[t]);
-    if (w) break;
+// Wavefront-cooperative pick: the smallest id in the highest non-empty level, -1 when
+// every super-vertex is scanned, -2 on an inconsistent bitmap.  All lanes return it.
+DEV int bit_pick(const St &s, int bound, unsigned long long *levelmask) {
+  const int lane = __lane_id();
+  if (s.nw1 == 1) {  // up to 4096 vertices: one summary word per level, read in parallel
+    uint64_t w1 = lane <= bound ? ld(&lvl1(s, lane)[0]) : 0ull;
+    uint64_t nz = __ballot(w1 != 0);
+    if (!nz) return -1;
+    int j = 63 - __clzll(nz);
+    w1 = __shfl(w1, j, 64);
+    int i0 = __ffsll((long long)w1) - 1;
+    uint64_t w0 = ld(&lvl0(s, j)[i0]);
+    if (!w0) return -2;
+    int x = i0 * 64 + __ffsll((long long)w0) - 1;
+    return x < s.n ? x : -2;
   }
-  if (!w) return -1;
-  int i1 = t * 64 + __ffsll((long long)w) - 1;
-  uint64_t w1 = ld(&lvl1(s, j)[i1]);
-  if (!w1) return -2;  // inconsistent summary (never expected)
-  int i0 = i1 * 64 + __ffsll((long long)w1) - 1;
-  uint64_t w0 = ld(&lvl0(s, j)[i0]);
-  if (!w0) return -2;
-  int x = i0 * 64 + __ffsll((long long)w0) - 1;
-  return x < s.n ? x : -2;
+  int x = -1;
+  if (lane == 0) {
+    unsigned long long lm = ld(levelmask);
+    if (lm) {
+      int j = 63 - __clzll(lm);
+      const uint64_t *L2 = lvl2(s, j);
+      uint64_t w = 0;
+      int t = 0;
+      for (; t < s.nw2; t++) {
+        w = ld(&L2[t]);
+        if (w) break;
+      }
+      if (!w) {
+        x = -2;
+      } else {
+        int i1 = t * 64 + __ffsll((long long)w) - 1;
+        uint64_t w1 = ld(&lvl1(s, j)[i1]);
+        if (!w1) {
+          x = -2;
+        } else {
+          int i0 = i1 * 64 + __ffsll((long long)w1) - 1;
+          uint64_t w0 = ld(&lvl0(s, j)[i0]);
+          x = w0 ? i0 * 64 + __ffsll((long long)w0) - 1 : -2;
+          if (x >= s.n) x = -2;
+        }
+      }
+    }
+  }
+  return __shfl(x, 0, 64);
 }
 
 // ---------------------------------------------------------------- helpers
+// optional phase profile: thread 0 adds the 100 MHz wall-clock time since *t to slot ph
+DEV void ph_mark(const ItemArgs &A, int ph, unsigned long long *t) {
+  if (!A.prof || threadIdx.x != 0) return;
+  unsigned long long now = wall_clock64();
+  atomicAdd(&A.cnt[CNT_PH + ph], now - *t);
+  *t = now;
+}
+
 DEV void err(const ItemArgs &A, int code) {
   atomicMin((long long *)&A.cnt[CNT_ERR], (long long)code);
 }
@@ -129,22 +213,16 @@ DEV void err(const ItemArgs &A, int code) {
 // Connected components of the item restricted to alive vertices (alive = A[i] >= kmin
 // when use_deg, else all).  B[i] = smallest vertex of i's component, -1 if dead.
 // Returns the number of components.
-DEV int item_cc(const St &s, const Arena &ar, const ItemDesc &d, bool use_deg, int kmin, Sh &sh) {
+DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   int n = s.n;
   for (int i = threadIdx.x; i < n; i += IB) {
     bool al = !use_deg || ld(&s.A[i]) >= kmin;
     st(&s.B[i], al ? i : -1);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += IB) {
-    if (ld(&s.B[i]) < 0) continue;
-    int64_t r0 = ar.rs[d.b + i];
-    int rdeg = ar.rd[d.b + i];
-    for (int e = 0; e < rdeg; e++) {
-      int j = ar.adj[r0 + e];
-      if (j < i && ld(&s.B[j]) >= 0) uf_unite(s.B, i, j);
-    }
-  }
+  for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int i, int, int j) {
+    if (j < i && ld(&s.B[i]) >= 0 && ld(&s.B[j]) >= 0) uf_unite(s.B, i, j);
+  });
   __syncthreads();
   int roots = 0;
   for (int i = threadIdx.x; i < n; i += IB) {
@@ -159,6 +237,8 @@ DEV int item_cc(const St &s, const Arena &ar, const ItemDesc &d, bool use_deg, i
 // ---------------------------------------------------------------- rebuild children
 // B[i]: child label (the child's smallest local id) or -1.  Children larger than gate
 // are compacted into the other arena inside [b, b+n) / [eb, eb+m) and pushed.
+// Uses A (sizes), D (child starts), E (new positions), C (row offsets by new position)
+// and F (write cursors by new position).
 DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gate, Sh &sh) {
   const Arena &ar = A.ar[d.depth & 1];
   const Arena &nx = A.ar[(d.depth + 1) & 1];
@@ -208,20 +288,20 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     }
   }
   __syncthreads();
-  // D[L] now holds start + size; restore starts
-  for (int i = threadIdx.x; i < n; i += IB)
-    if (ld(&s.B[i]) == i) st(&s.D[i], ld(&s.D[i]) - ld(&s.A[i]));
-  __syncthreads();
-  // new degrees by new position (C)
+  // D[L] now holds start + size; restore starts; clear new degrees and cursors
   for (int i = threadIdx.x; i < n; i += IB) {
-    int L = ld(&s.B[i]);
-    if (L < 0) continue;
-    int64_t r0 = ar.rs[d.b + i];
-    int rdeg = ar.rd[d.b + i];
-    int c = 0;
-    for (int e = 0; e < rdeg; e++) c += ld(&s.B[ar.adj[r0 + e]]) == L;
-    st(&s.C[ld(&s.E[i])], c);
+    if (ld(&s.B[i]) == i) st(&s.D[i], ld(&s.D[i]) - ld(&s.A[i]));
+    if (i < K) {
+      st(&s.C[i], 0);
+      st(&s.F[i], 0);
+    }
   }
+  __syncthreads();
+  // new degrees by new position (C); the rows are read from the arena
+  for_entries(s.R, n, s.m, [&](int e) { return s.adjg[e]; }, [&](int i, int, int j) {
+    int L = ld(&s.B[i]);
+    if (L >= 0 && ld(&s.B[j]) == L) atomicAdd(&s.C[ld(&s.E[i])], 1);
+  });
   __syncthreads();
   // row offsets by new position (exclusive scan of C, in place)
   long long ecarry = 0;
@@ -235,25 +315,25 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   }
   int M = (int)ecarry;
   __syncthreads();
-  // write the children's rows into the other arena
+  // vertex records of the children
   for (int i = threadIdx.x; i < n; i += IB) {
     int L = ld(&s.B[i]);
     if (L < 0) continue;
     int np = ld(&s.E[i]);
     int o = ld(&s.C[np]);
     int o1 = np + 1 < K ? ld(&s.C[np + 1]) : M;
-    int cstart = ld(&s.D[L]);
     nx.vtx[d.b + np] = ar.vtx[d.b + i];
     nx.rs[d.b + np] = d.eb + o;
     nx.rd[d.b + np] = o1 - o;
-    int64_t r0 = ar.rs[d.b + i];
-    int rdeg = ar.rd[d.b + i];
-    int64_t w = d.eb + o;
-    for (int e = 0; e < rdeg; e++) {
-      int j = ar.adj[r0 + e];
-      if (ld(&s.B[j]) == L) nx.adj[w++] = ld(&s.E[j]) - cstart;
-    }
   }
+  // rows: each kept entry takes the next slot of its row (order inside a row is free)
+  for_entries(s.R, n, s.m, [&](int e) { return s.adjg[e]; }, [&](int i, int, int j) {
+    int L = ld(&s.B[i]);
+    if (L < 0 || ld(&s.B[j]) != L) return;
+    int np = ld(&s.E[i]);
+    int slot = atomicAdd(&s.F[np], 1);
+    nx.adj[d.eb + ld(&s.C[np]) + slot] = ld(&s.E[j]) - ld(&s.D[L]);
+  });
   // descriptors of the children
   for (int i = threadIdx.x; i < n; i += IB) {
     if (ld(&s.B[i]) != i) continue;
@@ -268,6 +348,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     c.m = o1 - o;
     c.depth = d.depth + 1;
     c.flags = 0;
+    atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * c.n + 4LL * c.m));
     int slot = atomicAdd(A.out_count, 1);
     if (slot < A.out_cap) A.out[slot] = c;
     else err(A, WCC_ENOMEM);
@@ -277,13 +358,13 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
 
 // ---------------------------------------------------------------- k-core peel
 // A[i] ends as i's degree inside the surviving core (alive iff A[i] >= k).
-// Returns the number of removed vertices.
-DEV int item_peel(const St &s, const Arena &ar, const ItemDesc &d, int k, Sh &sh) {
+// Returns the number of removed vertices.  D and E hold the frontiers.
+DEV int item_peel(const St &s, int k, Sh &sh) {
   int n = s.n;
   if (threadIdx.x == 0) sh.vi[0] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += IB) {
-    int dg = ar.rd[d.b + i];
+    int dg = row_end(s, i) - ld(&s.R[i]);
     st(&s.A[i], dg);
     if (dg < k) st(&s.D[atomicAdd(&sh.vi[0], 1)], i);
   }
@@ -297,10 +378,9 @@ DEV int item_peel(const St &s, const Arena &ar, const ItemDesc &d, int k, Sh &sh
     __syncthreads();
     for (int f = threadIdx.x; f < cnt; f += IB) {
       int u = ld(&cur[f]);
-      int64_t r0 = ar.rs[d.b + u];
-      int rdeg = ar.rd[d.b + u];
-      for (int e = 0; e < rdeg; e++) {
-        int j = ar.adj[r0 + e];
+      int r0 = ld(&s.R[u]), r1 = row_end(s, u);
+      for (int e = r0; e < r1; e++) {
+        int j = adj_at(s, e);
         int old = atomicSub(&s.A[j], 1);
         if (old == k) st(&nxt[atomicAdd(&sh.vi[1], 1)], j);
       }
@@ -317,14 +397,65 @@ DEV int item_peel(const St &s, const Arena &ar, const ItemDesc &d, int k, Sh &sh
 }
 
 // ---------------------------------------------------------------- canonical min cut
+// One round's maximum-adjacency scan, run by wave 0.  Lists: owner x's entries are
+// [st[x], st[x]+len[x]) of `list` (LDS u16 when list16 != nullptr).  Contractible
+// entries are marked in s.mark.  coh: the list was written in this launch (read it past
+// the vector L1).  Returns the number of steps (< 0 on an inconsistency).
+DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
+                   const uint16_t *list16, bool coh, int bound, unsigned long long *levelmask) {
+  const int lane = threadIdx.x;
+  int steps = 0;
+  int cand = -1, cand_y = 0;  // prefetched first 64 entries of the likely next vertex
+  for (;;) {
+    int x = bit_pick(s, bound, levelmask);
+    if (x == -2 || (x >= 0 && steps >= s.n)) return -1;  // guard: at most n steps
+    if (x < 0) break;
+    steps++;
+    int top = ld(&s.A[x]);
+    top = top < bound ? top : bound;
+    int e0 = ld(&stv[x]);
+    int cnt = ld(&lenv[x]);
+    int y0 = -1;
+    bool have0 = false;
+    if (!list16 && x == cand) {
+      y0 = cand_y;
+      have0 = true;
+    }
+    if (lane <= top) bit_clear(s, lane, x, levelmask);
+    if (!list16) {
+      // prefetch the list of the vertex that would be picked if no key changed
+      cand = bit_pick(s, bound, levelmask);
+      if (cand >= 0) {
+        int ce0 = ld(&stv[cand]);
+        int ccnt = ld(&lenv[cand]);
+        cand_y = lane < ccnt ? (coh ? ld(&list[ce0 + lane]) : list[ce0 + lane]) : -1;
+      }
+    }
+    for (int base = 0; base < cnt; base += 64) {
+      int e = base + lane;
+      int y;
+      if (base == 0 && have0) y = y0;
+      else y = e < cnt ? (list16 ? (int)list16[e0 + e] : (coh ? ld(&list[e0 + e]) : list[e0 + e])) : -1;
+      if (e >= cnt || y < 0) continue;
+      if (!bit_test(s, 0, y)) continue;  // already scanned
+      int nw = atomicAdd(&s.A[y], 1) + 1;
+      if (nw <= bound) bit_set(s, nw, y, levelmask);
+      if (nw >= bound) st(&s.mark[e0 + e], 1);  // contractible: key reached the bound
+    }
+  }
+  return steps;
+}
+
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
-DEV int item_mincut(const ItemArgs &A, const St &s, const Arena &ar, const ItemDesc &d, int cap,
-                    Sh &sh, long long *steps_out, long long *rounds_out) {
+DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, Sh &sh,
+                    long long *steps_out, long long *rounds_out) {
   int n = s.n;
+  unsigned long long pt = A.prof ? wall_clock64() : 0;
   // Phase 0: minimum degree and its smallest vertex
   unsigned long long mv = ~0ull;
   for (int i = threadIdx.x; i < n; i += IB) {
-    unsigned long long v = ((unsigned long long)(uint32_t)ar.rd[d.b + i] << 32) | (uint32_t)i;
+    unsigned long long dg = (unsigned long long)(uint32_t)(row_end(s, i) - ld(&s.R[i]));
+    unsigned long long v = (dg << 32) | (uint32_t)i;
     mv = v < mv ? v : mv;
   }
   mv = block_min_u64<IB>(mv, sh.redu);
@@ -337,65 +468,54 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const Arena &ar, const ItemD
     bound = 1;  // give up on this item; the error is reported
   }
   if (bound > 1) {
-    // super-vertex ids: C[v]; round 1 is the item's own graph
-    for (int i = threadIdx.x; i < n; i += IB) st(&s.C[i], i);
+    // super-vertex ids C; round 1 scans the item's own rows (starts R, lengths D)
+    for (int i = threadIdx.x; i < n; i += IB) {
+      st(&s.C[i], i);
+      st(&s.D[i], row_end(s, i) - ld(&s.R[i]));
+    }
     bool first = true;
+    int total = s.m;  // entries in the current lists
     for (;;) {
-      // ---- round setup: keys, union-find, bitmaps (levels 0..bound)
+      ph_mark(A, 3, &pt);
+      // ---- round setup: keys, marks, bitmaps (levels 0..bound)
       int words = (bound + 1) * s.ls;
       for (int w = threadIdx.x; w < words; w += IB) st(&s.bits[w], (uint64_t)0);
       if (threadIdx.x == 0) sh.levelmask = 0;
-      for (int x = threadIdx.x; x < n; x += IB) {
-        st(&s.A[x], 0);
-        st(&s.B[x], x);
-      }
+      for (int x = threadIdx.x; x < n; x += IB) st(&s.A[x], 0);
+      for (int e = threadIdx.x; e < total; e += IB) st(&s.mark[e], 0);
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
         if (ld(&s.C[x]) == x) bit_set(s, 0, x, &sh.levelmask);
       __syncthreads();
-      // ---- maximum-adjacency scan
-      int round_steps = 0;
-      for (;;) {
-        if (threadIdx.x < 64) {
-          int x = 0;
-          if (threadIdx.x == 0) x = bit_pick(s, ld(&sh.levelmask));
-          x = __shfl(x, 0, 64);
-          if (x >= 0) {
-            int top = ld(&s.A[x]);
-            top = top < bound ? top : bound;
-            if ((int)threadIdx.x <= top) bit_clear(s, threadIdx.x, x, &sh.levelmask);
-          }
-          if (threadIdx.x == 0) sh.vi[2] = x;
-        }
-        __syncthreads();
-        int x = sh.vi[2];
-        if (x == -2 || (x >= 0 && round_steps >= n)) {  // guard: a scan takes at most n steps
-          if (threadIdx.x == 0) err(A, WCC_EHIP);
-          x = -1;
-        }
-        if (x < 0) break;
-        steps++;
-        round_steps++;
-        const int32_t *lst;
-        int cntx;
-        if (first) {
-          lst = ar.adj + ar.rs[d.b + x];
-          cntx = ar.rd[d.b + x];
-        } else {
-          lst = A.sEdge + d.eb + ld(&s.E[x]);
-          cntx = ld(&s.D[x]);
-        }
-        for (int e = threadIdx.x; e < cntx; e += IB) {
-          int y = first ? lst[e] : ld(&lst[e]);
-          if (!bit_test(s, 0, y)) continue;  // already scanned
-          int nw = atomicAdd(&s.A[y], 1) + 1;
-          if (nw <= bound) bit_set(s, nw, y, &sh.levelmask);
-          if (nw >= bound) uf_unite(s.B, x, y);  // contractible: key reached the bound
-        }
-        __syncthreads();
+      // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
+      const int32_t *stv = first ? s.R : s.E;
+      if (threadIdx.x < 64) {
+        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, false, bound, &sh.levelmask)
+                      : scan_round(s, stv, s.D, s.lists, nullptr, true, bound, &sh.levelmask);
+        if (threadIdx.x == 0) sh.vi[3] = r;
       }
+      __syncthreads();
+      if (sh.vi[3] < 0) {
+        if (threadIdx.x == 0) err(A, WCC_EHIP);
+        bound = 1;
+        s_kind = 0;
+        break;
+      }
+      steps += sh.vi[3];
+      ph_mark(A, 4, &pt);
       rounds++;
-      // ---- contraction: new id = smallest member of each merged group
+      // ---- contraction: union of every marked entry, new id = smallest member
+      for (int x = threadIdx.x; x < n; x += IB) st(&s.B[x], x);
+      __syncthreads();
+      if (first)
+        for_entries(stv, n, total, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
+          if (ld(&s.mark[e])) uf_unite(s.B, x, y);
+        });
+      else
+        for_entries(stv, n, total, [&](int e) { return ld(&s.lists[e]); }, [&](int x, int e, int y) {
+          if (ld(&s.mark[e])) uf_unite(s.B, x, y);
+        });
+      __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
         if (ld(&s.C[x]) == x) st(&s.B[x], uf_find(s.B, x));
       __syncthreads();
@@ -406,19 +526,16 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const Arena &ar, const ItemD
         reps += (c == v);
       }
       reps = block_sum<IB>(reps, sh.red);
+      ph_mark(A, 5, &pt);
       if (reps <= 1) break;
       first = false;
       // ---- crossing lists of the contracted graph (D = weighted degree, E = start)
       for (int x = threadIdx.x; x < n; x += IB) st(&s.D[x], 0);
       __syncthreads();
-      for (int v = threadIdx.x; v < n; v += IB) {
+      for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
         int a = ld(&s.C[v]);
-        int64_t r0 = ar.rs[d.b + v];
-        int rdeg = ar.rd[d.b + v];
-        int c = 0;
-        for (int e = 0; e < rdeg; e++) c += ld(&s.C[ar.adj[r0 + e]]) != a;
-        if (c) atomicAdd(&s.D[a], c);
-      }
+        if (ld(&s.C[u]) != a) atomicAdd(&s.D[a], 1);
+      });
       __syncthreads();
       int carry = 0;
       for (int base = 0; base < n; base += IB) {
@@ -432,17 +549,15 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const Arena &ar, const ItemD
         }
         carry += tot;
       }
+      total = carry;
       __syncthreads();
-      for (int v = threadIdx.x; v < n; v += IB) {
+      for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
         int a = ld(&s.C[v]);
-        int64_t r0 = ar.rs[d.b + v];
-        int rdeg = ar.rd[d.b + v];
-        for (int e = 0; e < rdeg; e++) {
-          int bb = ld(&s.C[ar.adj[r0 + e]]);
-          if (bb != a) st(&A.sEdge[d.eb + atomicAdd(&s.A[a], 1)], bb);
-        }
-      }
+        int bb = ld(&s.C[u]);
+        if (bb != a) st(&s.lists[atomicAdd(&s.A[a], 1)], bb);
+      });
       __syncthreads();
+      ph_mark(A, 6, &pt);
       // ---- degree check: smallest id of minimum weighted degree, strict improvement
       unsigned long long dm = ~0ull;
       for (int x = threadIdx.x; x < n; x += IB)
@@ -459,6 +574,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const Arena &ar, const ItemD
         __syncthreads();
         if (bound <= 1) break;
       }
+      ph_mark(A, 7, &pt);
     }
   }
   if (s_kind != 2)
@@ -470,49 +586,81 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const Arena &ar, const ItemD
 }
 
 // ---------------------------------------------------------------- one item
-DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int item_index, Sh &sh) {
+// Geometry and LDS footprint (32-bit words) of an item.
+struct Geo {
+  int lv, nw0, nw1, nw2, ls;
+  long long core;  // bitmaps + A, B, D, E, R
+  long long adj;   // 16-bit adjacency copy
+};
+DEV Geo item_geo(int n, long long m, int cap) {
+  Geo g;
+  g.lv = (cap < MAX_LEVEL ? cap : MAX_LEVEL) + 1;
+  g.nw0 = (n + 63) / 64;
+  g.nw1 = (g.nw0 + 63) / 64;
+  g.nw2 = (g.nw1 + 63) / 64;
+  g.ls = g.nw0 + g.nw1 + g.nw2;
+  g.core = 2LL * g.lv * g.ls + 5LL * n;
+  g.adj = n <= 65536 ? (m + 1) / 2 : (1LL << 40);
+  return g;
+}
+
+// LDS selects where the scan arrays live; instantiating both placements lets the
+// compiler emit LDS instructions (not generic ones) when they are in LDS.
+template <bool LDS>
+DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int item_index, Sh &sh) {
   const Arena &ar = A.ar[d.depth & 1];
   int n = d.n;
   int k = (int)wcc_k_of(A.crit, n, A.lin_num, A.lin_den);
   int set = A.split_only ? A.split_set[item_index] : -1;
   int cap = A.split_only ? A.split_cap[set] : k;
-  int lv = (cap < MAX_LEVEL ? cap : MAX_LEVEL) + 1;
+  Geo g = item_geo(n, d.m, cap);
   St s;
   s.n = n;
-  s.nw0 = (n + 63) / 64;
-  s.nw1 = (s.nw0 + 63) / 64;
-  s.nw2 = (s.nw1 + 63) / 64;
-  s.ls = s.nw0 + s.nw1 + s.nw2;
-  // LDS footprint in 32-bit words: 6 int arrays and the bitmaps (8-byte words)
-  long long need = 6LL * n + 2LL * lv * s.ls + 2;
-  if (need <= A.lds_words) {
-    uint64_t *bits = dyn;
-    int32_t *w = (int32_t *)(dyn + (size_t)lv * s.ls);
-    s.bits = bits;
+  s.m = (int)d.m;
+  s.nw0 = g.nw0;
+  s.nw1 = g.nw1;
+  s.nw2 = g.nw2;
+  s.ls = g.ls;
+  s.C = A.sC + d.b;
+  s.F = A.sF + d.b;
+  s.adjg = ar.adj + d.eb;
+  s.mark = A.sMark + d.eb;
+  s.lists = A.sEdge + d.eb;
+  s.adj16 = nullptr;
+  if constexpr (LDS) {
+    s.bits = dyn;
+    int32_t *w = (int32_t *)(dyn + (size_t)g.lv * g.ls);
     s.A = w;
     s.B = w + n;
-    s.C = w + 2 * n;
-    s.D = w + 3 * n;
-    s.E = w + 4 * n;
-    s.F = w + 5 * n;
+    s.D = w + 2 * n;
+    s.E = w + 3 * n;
+    s.R = w + 4 * n;
+    if (g.core + g.adj <= A.lds_words) s.adj16 = (uint16_t *)(w + 5 * n);
   } else {
     s.bits = A.gbits + (size_t)blockIdx.x * A.gbits_words;
-    if ((long long)lv * s.ls > A.gbits_words) {
+    if ((long long)g.lv * g.ls > A.gbits_words) {
       if (threadIdx.x == 0) err(A, WCC_EUNSUPPORTED);
       return;
     }
     s.A = A.sA + d.b;
     s.B = A.sB + d.b;
-    s.C = A.sC + d.b;
     s.D = A.sD + d.b;
     s.E = A.sE + d.b;
-    s.F = A.sF + d.b;
+    s.R = A.sG + d.b;
   }
   long long steps = 0, rounds = 0;
+  unsigned long long pt = A.prof ? wall_clock64() : 0;
+  // every item reads its rows at least once: vtx, rs, rd per vertex and one index per entry
+  if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * n + 4LL * d.m));
+  // row starts relative to eb, and the LDS copy of the adjacency when it fits
+  for (int i = threadIdx.x; i < n; i += IB) st(&s.R[i], (int32_t)(ar.rs[d.b + i] - d.eb));
+  if (s.adj16)
+    for (int e = threadIdx.x; e < s.m; e += IB) s.adj16[e] = (uint16_t)s.adjg[e];
+  __syncthreads();
 
   if (A.split_only) {
     // mincut_split: disconnected -> 0 and the component of the first vertex
-    int nc = item_cc(s, ar, d, false, 0, sh);
+    int nc = item_cc(s, false, 0, sh);
     int lam;
     if (n < 2) {
       lam = 0;
@@ -523,7 +671,7 @@ DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int i
       for (int i = threadIdx.x; i < n; i += IB) st(&s.F[i], (int32_t)(ld(&s.B[i]) == 0));
       __syncthreads();
     } else {
-      lam = item_mincut(A, s, ar, d, cap, sh, &steps, &rounds);
+      lam = item_mincut(A, s, d, cap, sh, &steps, &rounds);
     }
     int64_t p0 = A.split_pos[set];
     for (int i = threadIdx.x; i < n; i += IB) A.split_side[p0 + i] = (uint8_t)ld(&s.F[i]);
@@ -538,27 +686,32 @@ DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int i
   }
 
   if (d.flags & ITEM_CCR) {
-    int nc = item_cc(s, ar, d, false, 0, sh);
+    int nc = item_cc(s, false, 0, sh);
+    ph_mark(A, 0, &pt);
     if (nc > 1) {
       item_rebuild(A, s, d, A.s_pre, sh);
+      ph_mark(A, 9, &pt);
       return;
     }
     if (n <= A.s_pre) return;
   }
   if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ITEMS], 1ull);
   if (A.mode == WCC_PRUNE_KCORE) {
-    int removed = item_peel(s, ar, d, k, sh);
+    int removed = item_peel(s, k, sh);
+    ph_mark(A, 1, &pt);
     if (removed > 0) {
       if (removed < n) {
-        item_cc(s, ar, d, true, k, sh);
+        item_cc(s, true, k, sh);
         item_rebuild(A, s, d, A.s_post, sh);
       }
+      ph_mark(A, 2, &pt);
       return;
     }
   } else if (d.m == 0) {
     return;  // Alg. 3 tests only sets with at least one edge
   }
-  int lam = item_mincut(A, s, ar, d, k, sh, &steps, &rounds);
+  int lam = item_mincut(A, s, d, k, sh, &steps, &rounds);
+  pt = A.prof ? wall_clock64() : 0;
   // record: |S| and the order-free hash of S's global ids
   int ss = 0;
   unsigned long long hs = 0;
@@ -593,7 +746,10 @@ DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int i
   if (lam >= k) {  // cut > f(n): save the set under its smallest global id
     int key = ar.vtx[d.b];
     for (int i = threadIdx.x; i < n; i += IB) A.acc[ar.vtx[d.b + i]] = key;
-    if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ACCEPTED], 1ull);
+    if (threadIdx.x == 0) {
+      atomicAdd(&A.cnt[CNT_ACCEPTED], 1ull);
+      atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(4LL * n));
+    }
     __syncthreads();
     return;
   }
@@ -607,7 +763,17 @@ DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int i
   mC = block_min_u64<IB>(mC, sh.redu);
   for (int i = threadIdx.x; i < n; i += IB) st(&s.B[i], ld(&s.F[i]) ? (int)mS : (int)mC);
   __syncthreads();
+  ph_mark(A, 8, &pt);
   item_rebuild(A, s, d, A.s_post, sh);
+  ph_mark(A, 9, &pt);
+}
+
+DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int item_index, Sh &sh) {
+  int n = d.n;
+  int cap = A.split_only ? A.split_cap[A.split_set[item_index]] : (int)wcc_k_of(A.crit, n, A.lin_num, A.lin_den);
+  Geo g = item_geo(n, d.m, cap);
+  if (g.core <= A.lds_words) process_item_t<true>(A, d, dyn, item_index, sh);
+  else process_item_t<false>(A, d, dyn, item_index, sh);
 }
 
 __global__ void __launch_bounds__(IB) k_items(ItemArgs A) {
@@ -627,12 +793,14 @@ __global__ void __launch_bounds__(IB) k_items(ItemArgs A) {
 }
 
 // ---------------------------------------------------------------- item ordering
-// keys for a descending-size sort (largest items first)
-__global__ void k_item_keys(const ItemDesc *items, int32_t n, uint32_t *keys, uint32_t *vals) {
+// keys for a descending-size sort (largest items first); counts items above small_max
+__global__ void k_item_keys(const ItemDesc *items, int32_t n, uint32_t *keys, uint32_t *vals, int small_max,
+                            int32_t *nbig) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   keys[i] = 0x7fffffffu - (uint32_t)items[i].n;
   vals[i] = (uint32_t)i;
+  if (items[i].n > small_max) atomicAdd(nbig, 1);
 }
 __global__ void k_item_gather(const ItemDesc *in, const uint32_t *order, int32_t n, ItemDesc *out,
                               const int32_t *set_in, int32_t *set_out) {
@@ -657,6 +825,14 @@ __global__ void k_relabel(const int32_t *acc, const int32_t *rank, int64_t N, in
 }  // namespace
 
 int items_block() { return IB; }
+
+// LDS words a workgroup needs to keep an item's scan arrays of n vertices (cut cap `cap`)
+// in LDS (the 16-bit adjacency copy is optional on top of this)
+int64_t items_lds_words(int64_t n, int cap) {
+  int64_t nw0 = (n + 63) / 64, nw1 = (nw0 + 63) / 64, nw2 = (nw1 + 63) / 64;
+  int lv = (cap < MAX_LEVEL ? cap : MAX_LEVEL) + 1;
+  return 5 * n + 2 * (int64_t)lv * (nw0 + nw1 + nw2);
+}
 int items_max_level() { return MAX_LEVEL; }
 
 // words of 64-bit bitmap storage one workgroup needs for an item of n vertices
@@ -668,6 +844,11 @@ int64_t items_bitmap_words(int64_t n, int cap) {
 
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
   if (A.nitems <= 0) return WCC_OK;
+  static size_t attr_set = 0;
+  if (lds_bytes > 65536 && lds_bytes > attr_set) {
+    HIP_TRY(hipFuncSetAttribute((const void *)k_items, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    attr_set = lds_bytes;
+  }
   hipLaunchKernelGGL(k_items, dim3(grid), dim3(IB), lds_bytes, s, A);
   HIP_TRY(hipGetLastError());
   return WCC_OK;
@@ -675,12 +856,12 @@ int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
 
 int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t *set_in, int32_t *set_out,
                     uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
-                    hipStream_t s, int max_n) {
+                    hipStream_t s, int small_max, int32_t *nbig) {
   if (n <= 0) return WCC_OK;
-  hipLaunchKernelGGL(k_item_keys, dim3((n + 255) / 256), dim3(256), 0, s, in, n, k1, v1);
+  HIP_TRY(hipMemsetAsync(nbig, 0, sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_item_keys, dim3((n + 255) / 256), dim3(256), 0, s, in, n, k1, v1, small_max, nbig);
   HIP_TRY(hipGetLastError());
   int bits = 31, alt = 0;
-  (void)max_n;
   int rc = prim_radix_sort_pairs(k1, v1, k2, v2, n, bits, tmp, tmp_bytes, s, &alt);
   if (rc) return rc;
   hipLaunchKernelGGL(k_item_gather, dim3((n + 255) / 256), dim3(256), 0, s, in, alt ? v2 : v1, n, out,
