@@ -401,11 +401,11 @@ int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, 
   st.item_alg_bytes = (int64_t)hc[CNT_ALG_BYTES];
   if (A.prof) {
     static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
-                                  "lists", "degree", "record", "split-rebuild", "", "", "scanned-entries"};
+                                  "lists", "degree", "record", "split-rebuild", "steps", "prefetch-hits", "rounds"};
     fprintf(stderr, "[wcc phase ms, summed over workgroups]");
     for (int i = 0; i < 13; i++)
       if (names[i][0])
-        fprintf(stderr, " %s=%.2f", names[i], i == 12 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
+        fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
     fprintf(stderr, "\n");
   }
   if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];

@@ -52,13 +52,30 @@ struct St {
   uint64_t *bits;              // LDS or global
   uint16_t *adj16;             // LDS copy of the item's adjacency, or nullptr
   const int32_t *adjg;         // the item's adjacency in the arena (entry 0 = eb)
-  uint8_t *mark;               // global, entry-indexed contraction marks
+  uint8_t *mark;               // global, entry-indexed contraction marks (if no markbits)
+  uint32_t *markbits;          // LDS bit array of contraction marks, or nullptr
   int32_t *lists;              // global, entry-indexed crossing lists (rounds >= 2)
   int n, m;
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
+  bool pf;                     // accumulate this item's phase profile
 };
 
 DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ld(&s.R[x + 1]) : s.m; }
+
+// contraction marks: one bit per list entry in LDS when it fits, else one byte in global
+DEV void mark_set(const St &s, int e) {
+  if (s.markbits) atomicOr(&s.markbits[e >> 5], 1u << (e & 31));
+  else st(&s.mark[e], 1);
+}
+DEV bool mark_get(const St &s, int e) {
+  return s.markbits ? ((ld(&s.markbits[e >> 5]) >> (e & 31)) & 1u) : ld(&s.mark[e]) != 0;
+}
+DEV void mark_clear(const St &s, int total) {
+  if (s.markbits)
+    for (int w = threadIdx.x; w < (total + 31) / 32; w += IB) st(&s.markbits[w], 0u);
+  else
+    for (int e = threadIdx.x; e < total; e += IB) st(&s.mark[e], 0);
+}
 DEV int adj_at(const St &s, int e) { return s.adj16 ? (int)s.adj16[e] : s.adjg[e]; }
 
 DEV int uf_find(int32_t *P, int x) {
@@ -151,9 +168,11 @@ DEV void bit_clear(const St &s, int j, int x, unsigned long long *levelmask) {
 DEV bool bit_test(const St &s, int j, int y) { return (ld(&lvl0(s, j)[y >> 6]) >> (y & 63)) & 1ull; }
 
 // Wavefront-cooperative pick: the smallest id in the highest non-empty level, -1 when
-// every super-vertex is scanned, -2 on an inconsistent bitmap.  All lanes return it.
-DEV int bit_pick(const St &s, int bound, unsigned long long *levelmask) {
+// every super-vertex is scanned, -2 on an inconsistent bitmap.  All lanes return it;
+// *j_out receives its level.
+DEV int bit_pick(const St &s, int bound, unsigned long long *levelmask, int *j_out) {
   const int lane = __lane_id();
+  *j_out = 0;
   if (s.nw1 == 1) {  // up to 4096 vertices: one summary word per level, read in parallel
     uint64_t w1 = lane <= bound ? ld(&lvl1(s, lane)[0]) : 0ull;
     uint64_t nz = __ballot(w1 != 0);
@@ -163,14 +182,16 @@ DEV int bit_pick(const St &s, int bound, unsigned long long *levelmask) {
     int i0 = __ffsll((long long)w1) - 1;
     uint64_t w0 = ld(&lvl0(s, j)[i0]);
     if (!w0) return -2;
+    *j_out = j;
     int x = i0 * 64 + __ffsll((long long)w0) - 1;
     return x < s.n ? x : -2;
   }
-  int x = -1;
+  int x = -1, jj = 0;
   if (lane == 0) {
     unsigned long long lm = ld(levelmask);
     if (lm) {
       int j = 63 - __clzll(lm);
+      jj = j;
       const uint64_t *L2 = lvl2(s, j);
       uint64_t w = 0;
       int t = 0;
@@ -194,13 +215,32 @@ DEV int bit_pick(const St &s, int bound, unsigned long long *levelmask) {
       }
     }
   }
+  *j_out = __shfl(jj, 0, 64);
   return __shfl(x, 0, 64);
+}
+
+DEV int wave_max_i(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    int t = __shfl_xor(v, d, 64);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+DEV int wave_min_i(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    int t = __shfl_xor(v, d, 64);
+    v = t < v ? t : v;
+  }
+  return v;
 }
 
 // ---------------------------------------------------------------- helpers
 // optional phase profile: thread 0 adds the 100 MHz wall-clock time since *t to slot ph
-DEV void ph_mark(const ItemArgs &A, int ph, unsigned long long *t) {
-  if (!A.prof || threadIdx.x != 0) return;
+DEV void ph_mark(const ItemArgs &A, const St &s, int ph, unsigned long long *t) {
+  (void)A;
+  if (!s.pf || threadIdx.x != 0) return;
   unsigned long long now = wall_clock64();
   atomicAdd(&A.cnt[CNT_PH + ph], now - *t);
   *t = now;
@@ -397,52 +437,100 @@ DEV int item_peel(const St &s, int k, Sh &sh) {
 }
 
 // ---------------------------------------------------------------- canonical min cut
+constexpr int32_t SCANNED = -(1 << 30);  // key of a scanned super-vertex (stays negative)
+
+// Effect of one list entry x -> y whose increment left y's key at nw > 0.
+DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, unsigned long long *levelmask,
+                    int *bl, int *by) {
+  int lv = nw < bound ? nw : bound;
+  if (nw <= bound) bit_set(s, nw, y, levelmask);
+  if (nw == bound) st(&s.B[y], x);          // contractible, first for y: parent
+  else if (nw > bound) mark_set(s, e);      // contractible, extra edge
+  if (lv > *bl || (lv == *bl && y < *by)) {
+    *bl = lv;
+    *by = y;
+  }
+}
+
 // One round's maximum-adjacency scan, run by wave 0.  Lists: owner x's entries are
-// [st[x], st[x]+len[x]) of `list` (LDS u16 when list16 != nullptr).  Contractible
+// [st[x], st[x]+len[x]) of `list` (LDS u16 when list16 != nullptr).  The contractible
+// entries form a forest plus extra edges: when a key first reaches the bound, the
+// scanned vertex becomes the parent (B) of the unscanned one; later contractible
 // entries are marked in s.mark.  coh: the list was written in this launch (read it past
 // the vector L1).  Returns the number of steps (< 0 on an inconsistency).
+//
+// The next vertex usually follows from the step itself, without reading the bitmaps:
+// x was the smallest member of the highest non-empty level jx.  If this step raised some
+// keys above jx, the new top level holds exactly those vertices, and the next vertex is
+// the smallest of them.  Otherwise the top level stays jx and the next vertex is the
+// smaller of x's successor in its own bitmap word and the vertices raised to jx now;
+// when that successor does not exist, the bitmaps are searched.
 DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
-                   const uint16_t *list16, bool coh, int bound, unsigned long long *levelmask) {
+                   const uint16_t *list16, bool coh, int bound, unsigned long long *levelmask,
+                   unsigned long long *prof_hits) {
   const int lane = threadIdx.x;
-  int steps = 0;
-  int cand = -1, cand_y = 0;  // prefetched first 64 entries of the likely next vertex
+  int steps = 0, hits = 0;
+  int cand = -1, cand_y = -1;  // prefetched first 64 entries of the likely next vertex
+  int x = -1, jx = 0;          // next vertex when already known, and its level
   for (;;) {
-    int x = bit_pick(s, bound, levelmask);
-    if (x == -2 || (x >= 0 && steps >= s.n)) return -1;  // guard: at most n steps
-    if (x < 0) break;
+    if (x < 0) {
+      x = bit_pick(s, bound, levelmask, &jx);
+      if (x == -2) return -1;
+      if (x < 0) break;
+    }
+    if (steps >= s.n) return -1;  // guard: a scan takes at most n steps
     steps++;
-    int top = ld(&s.A[x]);
-    top = top < bound ? top : bound;
+    int key = ld(&s.A[x]);
     int e0 = ld(&stv[x]);
     int cnt = ld(&lenv[x]);
-    int y0 = -1;
-    bool have0 = false;
-    if (!list16 && x == cand) {
-      y0 = cand_y;
-      have0 = true;
+    uint64_t w0 = ld(&lvl0(s, jx)[x >> 6]);
+    int top = key < bound ? key : bound;
+    bool have0 = !list16 && x == cand;
+    hits += have0;
+    // first 64 entries of x's list: from LDS, from the prefetch, or loaded now -- before
+    // the next prefetch is issued, so that waiting for them never waits for it
+    int y = -1;
+    if (lane < cnt) {
+      if (list16) y = list16[e0 + lane];
+      else if (have0) y = cand_y;
+      else y = coh ? ld(&list[e0 + lane]) : list[e0 + lane];
     }
+    int nw = lane < cnt ? atomicAdd(&s.A[y], 1) + 1 : 0;
+    // y is complete here; re-defining it in an empty asm statement keeps the compiler
+    // from waiting again (for the prefetch issued next) where y is used below
+    asm volatile("" : "+v"(y));
+    if (lane == 0) st(&s.A[x], SCANNED);
     if (lane <= top) bit_clear(s, lane, x, levelmask);
-    if (!list16) {
-      // prefetch the list of the vertex that would be picked if no key changed
-      cand = bit_pick(s, bound, levelmask);
-      if (cand >= 0) {
-        int ce0 = ld(&stv[cand]);
-        int ccnt = ld(&lenv[cand]);
-        cand_y = lane < ccnt ? (coh ? ld(&list[ce0 + lane]) : list[ce0 + lane]) : -1;
-      }
+    uint64_t rest = w0 & ~(1ull << (x & 63));
+    cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
+    if (!list16 && cand >= 0) {
+      int ce0 = ld(&stv[cand]);
+      int ccnt = ld(&lenv[cand]);
+      cand_y = lane < ccnt ? (coh ? ld(&list[ce0 + lane]) : list[ce0 + lane]) : -1;
     }
-    for (int base = 0; base < cnt; base += 64) {
+    int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
+    // the first chunk is handled in its own straight-line block so that no wait for the
+    // prefetch in flight is placed in it
+    if (nw > 0) scan_entry(s, x, y, nw, e0 + lane, bound, levelmask, &bl, &by);
+    for (int base = 64; base < cnt; base += 64) {
       int e = base + lane;
-      int y;
-      if (base == 0 && have0) y = y0;
-      else y = e < cnt ? (list16 ? (int)list16[e0 + e] : (coh ? ld(&list[e0 + e]) : list[e0 + e])) : -1;
-      if (e >= cnt || y < 0) continue;
-      if (!bit_test(s, 0, y)) continue;  // already scanned
-      int nw = atomicAdd(&s.A[y], 1) + 1;
-      if (nw <= bound) bit_set(s, nw, y, levelmask);
-      if (nw >= bound) st(&s.mark[e0 + e], 1);  // contractible: key reached the bound
+      if (e >= cnt) break;
+      int y2 = list16 ? (int)list16[e0 + e] : (coh ? ld(&list[e0 + e]) : list[e0 + e]);
+      int nw2 = atomicAdd(&s.A[y2], 1) + 1;
+      if (nw2 > 0) scan_entry(s, x, y2, nw2, e0 + e, bound, levelmask, &bl, &by);
     }
+    int M = wave_max_i(bl);
+    int nx = -1;
+    if (M > jx) {
+      nx = wave_min_i(bl == M ? by : 0x7fffffff);
+      jx = M;
+    } else if (cand >= 0) {
+      int m = wave_min_i(bl == jx ? by : 0x7fffffff);
+      nx = m < cand ? m : cand;
+    }
+    x = nx;
   }
+  if (prof_hits) *prof_hits += hits;
   return steps;
 }
 
@@ -450,7 +538,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
 DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, Sh &sh,
                     long long *steps_out, long long *rounds_out) {
   int n = s.n;
-  unsigned long long pt = A.prof ? wall_clock64() : 0;
+  unsigned long long pt = s.pf ? wall_clock64() : 0;
   // Phase 0: minimum degree and its smallest vertex
   unsigned long long mv = ~0ull;
   for (int i = threadIdx.x; i < n; i += IB) {
@@ -476,13 +564,16 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
     bool first = true;
     int total = s.m;  // entries in the current lists
     for (;;) {
-      ph_mark(A, 3, &pt);
+      ph_mark(A, s, 3, &pt);
       // ---- round setup: keys, marks, bitmaps (levels 0..bound)
       int words = (bound + 1) * s.ls;
       for (int w = threadIdx.x; w < words; w += IB) st(&s.bits[w], (uint64_t)0);
       if (threadIdx.x == 0) sh.levelmask = 0;
-      for (int x = threadIdx.x; x < n; x += IB) st(&s.A[x], 0);
-      for (int e = threadIdx.x; e < total; e += IB) st(&s.mark[e], 0);
+      for (int x = threadIdx.x; x < n; x += IB) {
+        st(&s.A[x], 0);
+        st(&s.B[x], x);
+      }
+      mark_clear(s, total);
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
         if (ld(&s.C[x]) == x) bit_set(s, 0, x, &sh.levelmask);
@@ -490,8 +581,14 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
       const int32_t *stv = first ? s.R : s.E;
       if (threadIdx.x < 64) {
-        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, false, bound, &sh.levelmask)
-                      : scan_round(s, stv, s.D, s.lists, nullptr, true, bound, &sh.levelmask);
+        unsigned long long hits = 0;
+        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, false, bound, &sh.levelmask, &hits)
+                      : scan_round(s, stv, s.D, s.lists, nullptr, true, bound, &sh.levelmask, &hits);
+        if (s.pf && threadIdx.x == 0) {
+          atomicAdd(&A.cnt[CNT_PH + 10], (unsigned long long)(r > 0 ? r : 0));
+          atomicAdd(&A.cnt[CNT_PH + 11], hits);
+          atomicAdd(&A.cnt[CNT_PH + 12], 1ull);
+        }
         if (threadIdx.x == 0) sh.vi[3] = r;
       }
       __syncthreads();
@@ -502,31 +599,40 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
         break;
       }
       steps += sh.vi[3];
-      ph_mark(A, 4, &pt);
+      ph_mark(A, s, 4, &pt);
       rounds++;
-      // ---- contraction: union of every marked entry, new id = smallest member
-      for (int x = threadIdx.x; x < n; x += IB) st(&s.B[x], x);
+      // ---- contraction: parent forest, then unions of the extra marked entries; the new
+      // id of a merged group is its smallest member (A serves as the group minimum)
+      for (int x = threadIdx.x; x < n; x += IB)
+        if (ld(&s.C[x]) == x) {
+          st(&s.B[x], uf_find(s.B, x));
+          st(&s.A[x], 0x7fffffff);
+        }
       __syncthreads();
       if (first)
         for_entries(stv, n, total, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
-          if (ld(&s.mark[e])) uf_unite(s.B, x, y);
+          if (mark_get(s, e)) uf_unite(s.B, x, y);
         });
       else
         for_entries(stv, n, total, [&](int e) { return ld(&s.lists[e]); }, [&](int x, int e, int y) {
-          if (ld(&s.mark[e])) uf_unite(s.B, x, y);
+          if (mark_get(s, e)) uf_unite(s.B, x, y);
         });
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
-        if (ld(&s.C[x]) == x) st(&s.B[x], uf_find(s.B, x));
+        if (ld(&s.C[x]) == x) {
+          int r = uf_find(s.B, x);
+          st(&s.B[x], r);
+          atomicMin(&s.A[r], x);
+        }
       __syncthreads();
       int reps = 0;
       for (int v = threadIdx.x; v < n; v += IB) {
-        int c = ld(&s.B[ld(&s.C[v])]);
+        int c = ld(&s.A[ld(&s.B[ld(&s.C[v])])]);
         st(&s.C[v], c);
         reps += (c == v);
       }
       reps = block_sum<IB>(reps, sh.red);
-      ph_mark(A, 5, &pt);
+      ph_mark(A, s, 5, &pt);
       if (reps <= 1) break;
       first = false;
       // ---- crossing lists of the contracted graph (D = weighted degree, E = start)
@@ -557,7 +663,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
         if (bb != a) st(&s.lists[atomicAdd(&s.A[a], 1)], bb);
       });
       __syncthreads();
-      ph_mark(A, 6, &pt);
+      ph_mark(A, s, 6, &pt);
       // ---- degree check: smallest id of minimum weighted degree, strict improvement
       unsigned long long dm = ~0ull;
       for (int x = threadIdx.x; x < n; x += IB)
@@ -574,7 +680,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
         __syncthreads();
         if (bound <= 1) break;
       }
-      ph_mark(A, 7, &pt);
+      ph_mark(A, s, 7, &pt);
     }
   }
   if (s_kind != 2)
@@ -590,6 +696,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
 struct Geo {
   int lv, nw0, nw1, nw2, ls;
   long long core;  // bitmaps + A, B, D, E, R
+  long long marks; // contraction mark bits
   long long adj;   // 16-bit adjacency copy
 };
 DEV Geo item_geo(int n, long long m, int cap) {
@@ -600,6 +707,7 @@ DEV Geo item_geo(int n, long long m, int cap) {
   g.nw2 = (g.nw1 + 63) / 64;
   g.ls = g.nw0 + g.nw1 + g.nw2;
   g.core = 2LL * g.lv * g.ls + 5LL * n;
+  g.marks = (m + 31) / 32 + 1;
   g.adj = n <= 65536 ? (m + 1) / 2 : (1LL << 40);
   return g;
 }
@@ -635,7 +743,9 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     s.D = w + 2 * n;
     s.E = w + 3 * n;
     s.R = w + 4 * n;
-    if (g.core + g.adj <= A.lds_words) s.adj16 = (uint16_t *)(w + 5 * n);
+    s.markbits = nullptr;
+    if (g.core + g.marks <= A.lds_words) s.markbits = (uint32_t *)(w + 5 * n);
+    if (g.core + g.marks + g.adj <= A.lds_words) s.adj16 = (uint16_t *)(w + 5 * n + g.marks);
   } else {
     s.bits = A.gbits + (size_t)blockIdx.x * A.gbits_words;
     if ((long long)g.lv * g.ls > A.gbits_words) {
@@ -647,9 +757,11 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     s.D = A.sD + d.b;
     s.E = A.sE + d.b;
     s.R = A.sG + d.b;
+    s.markbits = nullptr;
   }
   long long steps = 0, rounds = 0;
-  unsigned long long pt = A.prof ? wall_clock64() : 0;
+  s.pf = A.prof == 1 || (A.prof == 2 && item_index == 0);
+  unsigned long long pt = s.pf ? wall_clock64() : 0;
   // every item reads its rows at least once: vtx, rs, rd per vertex and one index per entry
   if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * n + 4LL * d.m));
   // row starts relative to eb, and the LDS copy of the adjacency when it fits
@@ -687,10 +799,10 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
 
   if (d.flags & ITEM_CCR) {
     int nc = item_cc(s, false, 0, sh);
-    ph_mark(A, 0, &pt);
+    ph_mark(A, s, 0, &pt);
     if (nc > 1) {
       item_rebuild(A, s, d, A.s_pre, sh);
-      ph_mark(A, 9, &pt);
+      ph_mark(A, s, 9, &pt);
       return;
     }
     if (n <= A.s_pre) return;
@@ -698,20 +810,20 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ITEMS], 1ull);
   if (A.mode == WCC_PRUNE_KCORE) {
     int removed = item_peel(s, k, sh);
-    ph_mark(A, 1, &pt);
+    ph_mark(A, s, 1, &pt);
     if (removed > 0) {
       if (removed < n) {
         item_cc(s, true, k, sh);
         item_rebuild(A, s, d, A.s_post, sh);
       }
-      ph_mark(A, 2, &pt);
+      ph_mark(A, s, 2, &pt);
       return;
     }
   } else if (d.m == 0) {
     return;  // Alg. 3 tests only sets with at least one edge
   }
   int lam = item_mincut(A, s, d, k, sh, &steps, &rounds);
-  pt = A.prof ? wall_clock64() : 0;
+  pt = s.pf ? wall_clock64() : 0;
   // record: |S| and the order-free hash of S's global ids
   int ss = 0;
   unsigned long long hs = 0;
@@ -763,9 +875,9 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   mC = block_min_u64<IB>(mC, sh.redu);
   for (int i = threadIdx.x; i < n; i += IB) st(&s.B[i], ld(&s.F[i]) ? (int)mS : (int)mC);
   __syncthreads();
-  ph_mark(A, 8, &pt);
+  ph_mark(A, s, 8, &pt);
   item_rebuild(A, s, d, A.s_post, sh);
-  ph_mark(A, 9, &pt);
+  ph_mark(A, s, 9, &pt);
 }
 
 DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int item_index, Sh &sh) {
