@@ -406,7 +406,9 @@ int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, 
     for (int i = 0; i < 13; i++)
       if (names[i][0])
         fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
-    fprintf(stderr, "\n");
+    fprintf(stderr, "\n[wcc scan segments ms] pick=%.2f load+key=%.2f clear+prefetch=%.2f chunk0=%.2f more=%.2f next=%.2f\n",
+            hc[CNT_PH + 16] / 1e5, hc[CNT_PH + 17] / 1e5, hc[CNT_PH + 18] / 1e5, hc[CNT_PH + 19] / 1e5,
+            hc[CNT_PH + 20] / 1e5, hc[CNT_PH + 21] / 1e5);
   }
   if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
   st.ms_total = ms_since(t0);

@@ -86,7 +86,7 @@ enum : int32_t {
   CNT_ERR,  // first error code seen by a kernel (atomicMin of negative codes)
   CNT_ALG_BYTES,  // algorithmic bytes of the item launches (reads + writes)
   CNT_PH,         // 16 slots: optional per-phase clock totals (profiling builds of a run)
-  CNT_PH_END = CNT_PH + 16,
+  CNT_PH_END = CNT_PH + 32,
   CNT_NUM
 };
 

@@ -41,7 +41,7 @@ struct Sh {
   int red[NW + 1];
   long long red64[NW + 1];
   unsigned long long redu[NW + 1];
-  unsigned long long levelmask;
+  int lcnt[64];                // members per scan level
   unsigned long long hsum;
   int vi[8];
 };
@@ -58,6 +58,7 @@ struct St {
   int n, m;
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
   bool pf;                     // accumulate this item's phase profile
+  unsigned long long *prof_cnt; // segment timing slots (profiling runs only)
 };
 
 DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ld(&s.R[x + 1]) : s.m; }
@@ -138,103 +139,77 @@ DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
 // ---------------------------------------------------------------- bitmap levels
 DEV uint64_t *lvl0(const St &s, int j) { return s.bits + (size_t)j * s.ls; }
 DEV uint64_t *lvl1(const St &s, int j) { return s.bits + (size_t)j * s.ls + s.nw0; }
-DEV uint64_t *lvl2(const St &s, int j) { return s.bits + (size_t)j * s.ls + s.nw0 + s.nw1; }
 
-DEV void bit_set(const St &s, int j, int y, unsigned long long *levelmask) {
-  unsigned long long old = atomicOr((unsigned long long *)&lvl0(s, j)[y >> 6], 1ull << (y & 63));
-  if (old) return;
-  old = atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
-  if (old || s.nw1 == 1) return;
-  old = atomicOr((unsigned long long *)&lvl2(s, j)[y >> 18], 1ull << ((y >> 12) & 63));
-  if (old) return;
-  atomicOr(levelmask, 1ull << j);
+// Level j: a bit per vertex (L0), a summary bit per L0 word that is set whenever a bit
+// of that word is set but only cleared lazily (L1), and the exact member count lcnt[j].
+// Setting and clearing need no returned values, so they never stall the scan.
+DEV void bit_set(const St &s, int j, int y, int *lcnt) {
+  atomicOr((unsigned long long *)&lvl0(s, j)[y >> 6], 1ull << (y & 63));
+  atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
+  atomicAdd(&lcnt[j], 1);
 }
 
-DEV void bit_clear(const St &s, int j, int x, unsigned long long *levelmask) {
-  unsigned long long b = 1ull << (x & 63);
-  unsigned long long old = atomicAnd((unsigned long long *)&lvl0(s, j)[x >> 6], ~b);
-  if (old != b) return;
-  b = 1ull << ((x >> 6) & 63);
-  old = atomicAnd((unsigned long long *)&lvl1(s, j)[x >> 12], ~b);
-  if (old != b || s.nw1 == 1) return;
-  b = 1ull << ((x >> 12) & 63);
-  old = atomicAnd((unsigned long long *)&lvl2(s, j)[x >> 18], ~b);
-  if (old != b) return;
-  for (int t = 0; t < s.nw2; t++)
-    if (ld(&lvl2(s, j)[t])) return;
-  atomicAnd(levelmask, ~(1ull << j));
+DEV void bit_clear(const St &s, int j, int x, int *lcnt) {
+  atomicAnd((unsigned long long *)&lvl0(s, j)[x >> 6], ~(1ull << (x & 63)));
+  atomicSub(&lcnt[j], 1);
 }
 
-DEV bool bit_test(const St &s, int j, int y) { return (ld(&lvl0(s, j)[y >> 6]) >> (y & 63)) & 1ull; }
+DEV uint64_t readlane64(uint64_t v, int l) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), l) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+}
 
 // Wavefront-cooperative pick: the smallest id in the highest non-empty level, -1 when
 // every super-vertex is scanned, -2 on an inconsistent bitmap.  All lanes return it;
-// *j_out receives its level.
-DEV int bit_pick(const St &s, int bound, unsigned long long *levelmask, int *j_out) {
+// *j_out receives its level.  Summary words whose L0 words all turned empty are reset.
+DEV int bit_pick(const St &s, int bound, int *lcnt, int *j_out) {
   const int lane = __lane_id();
   *j_out = 0;
-  if (s.nw1 == 1) {  // up to 4096 vertices: one summary word per level, read in parallel
-    uint64_t w1 = lane <= bound ? ld(&lvl1(s, lane)[0]) : 0ull;
-    uint64_t nz = __ballot(w1 != 0);
-    if (!nz) return -1;
-    int j = 63 - __clzll(nz);
-    w1 = __shfl(w1, j, 64);
-    int i0 = __ffsll((long long)w1) - 1;
-    uint64_t w0 = ld(&lvl0(s, j)[i0]);
-    if (!w0) return -2;
-    *j_out = j;
-    int x = i0 * 64 + __ffsll((long long)w0) - 1;
-    return x < s.n ? x : -2;
-  }
-  int x = -1, jj = 0;
-  if (lane == 0) {
-    unsigned long long lm = ld(levelmask);
-    if (lm) {
-      int j = 63 - __clzll(lm);
-      jj = j;
-      const uint64_t *L2 = lvl2(s, j);
-      uint64_t w = 0;
-      int t = 0;
-      for (; t < s.nw2; t++) {
-        w = ld(&L2[t]);
-        if (w) break;
+  int c = lane <= bound ? ld(&lcnt[lane]) : 0;
+  uint64_t nz = __ballot(c > 0);
+  if (!nz) return -1;
+  int j = 63 - __clzll(nz);
+  *j_out = j;
+  uint64_t *L1 = lvl1(s, j);
+  const uint64_t *L0 = lvl0(s, j);
+  for (int c0 = 0; c0 < s.nw1; c0 += 64) {
+    uint64_t w1 = c0 + lane < s.nw1 ? ld(&L1[c0 + lane]) : 0ull;
+    uint64_t m1 = __ballot(w1 != 0);
+    while (m1) {
+      int l = __ffsll((long long)m1) - 1;
+      int i1 = c0 + l;
+      int i0 = i1 * 64 + lane;
+      uint64_t w0 = i0 < s.nw0 ? ld(&L0[i0]) : 0ull;
+      uint64_t m0 = __ballot(w0 != 0);
+      if (m0) {
+        int b = __ffsll((long long)m0) - 1;
+        uint64_t wsel = readlane64(w0, b);
+        int x = (i1 * 64 + b) * 64 + __ffsll((long long)wsel) - 1;
+        return x < s.n ? x : -2;
       }
-      if (!w) {
-        x = -2;
-      } else {
-        int i1 = t * 64 + __ffsll((long long)w) - 1;
-        uint64_t w1 = ld(&lvl1(s, j)[i1]);
-        if (!w1) {
-          x = -2;
-        } else {
-          int i0 = i1 * 64 + __ffsll((long long)w1) - 1;
-          uint64_t w0 = ld(&lvl0(s, j)[i0]);
-          x = w0 ? i0 * 64 + __ffsll((long long)w0) - 1 : -2;
-          if (x >= s.n) x = -2;
-        }
-      }
+      if (lane == 0) st(&L1[i1], 0ull);  // stale summary word
+      m1 &= m1 - 1;
     }
   }
-  *j_out = __shfl(jj, 0, 64);
-  return __shfl(x, 0, 64);
+  return -2;
 }
 
-DEV int wave_max_i(int v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    int t = __shfl_xor(v, d, 64);
-    v = t > v ? t : v;
-  }
-  return v;
+// Wavefront reductions without the LDS crossbar: DPP exchanges inside each row of 16
+// lanes (xor 1, xor 2, half-row mirror, row mirror), then the four row results are read
+// with readlane.  Call with all 64 lanes active; the result is uniform.
+template <bool MAX>
+DEV int wave_red_i(int v) {
+  auto op = [](int a, int b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+  int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return op(op(r0, r1), op(r2, r3));
 }
-DEV int wave_min_i(int v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    int t = __shfl_xor(v, d, 64);
-    v = t < v ? t : v;
-  }
-  return v;
-}
+DEV int wave_max_i(int v) { return wave_red_i<true>(v); }
+DEV int wave_min_i(int v) { return wave_red_i<false>(v); }
 
 // ---------------------------------------------------------------- helpers
 // optional phase profile: thread 0 adds the 100 MHz wall-clock time since *t to slot ph
@@ -440,10 +415,10 @@ DEV int item_peel(const St &s, int k, Sh &sh) {
 constexpr int32_t SCANNED = -(1 << 30);  // key of a scanned super-vertex (stays negative)
 
 // Effect of one list entry x -> y whose increment left y's key at nw > 0.
-DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, unsigned long long *levelmask,
+DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *lcnt,
                     int *bl, int *by) {
   int lv = nw < bound ? nw : bound;
-  if (nw <= bound) bit_set(s, nw, y, levelmask);
+  if (nw <= bound) bit_set(s, nw, y, lcnt);
   if (nw == bound) st(&s.B[y], x);          // contractible, first for y: parent
   else if (nw > bound) mark_set(s, e);      // contractible, extra edge
   if (lv > *bl || (lv == *bl && y < *by)) {
@@ -466,17 +441,29 @@ DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, unsigne
 // smaller of x's successor in its own bitmap word and the vertices raised to jx now;
 // when that successor does not exist, the bitmaps are searched.
 DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
-                   const uint16_t *list16, bool coh, int bound, unsigned long long *levelmask,
+                   const uint16_t *list16, bool coh, int bound, int *lcnt,
                    unsigned long long *prof_hits) {
   const int lane = threadIdx.x;
   int steps = 0, hits = 0;
   int cand = -1, cand_y = -1;  // prefetched first 64 entries of the likely next vertex
   int x = -1, jx = 0;          // next vertex when already known, and its level
+  // optional segment timing of the largest item (profiling runs only)
+  const bool tm = prof_hits != nullptr && s.pf;
+  unsigned long long tseg[7] = {0, 0, 0, 0, 0, 0, 0}, tl = 0;
+#define SEG(k, wait)                                                   \
+  if (tm) {                                                            \
+    asm volatile(wait ::: "memory");                                   \
+    unsigned long long tn = wall_clock64();                            \
+    tseg[k] += tn - tl;                                                \
+    tl = tn;                                                           \
+  }
+  if (tm) tl = wall_clock64();
   for (;;) {
     if (x < 0) {
-      x = bit_pick(s, bound, levelmask, &jx);
+      x = bit_pick(s, bound, lcnt, &jx);
       if (x == -2) return -1;
       if (x < 0) break;
+      SEG(0, "s_waitcnt lgkmcnt(0)")
     }
     if (steps >= s.n) return -1;  // guard: a scan takes at most n steps
     steps++;
@@ -499,8 +486,9 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     // y is complete here; re-defining it in an empty asm statement keeps the compiler
     // from waiting again (for the prefetch issued next) where y is used below
     asm volatile("" : "+v"(y));
+    SEG(1, "s_waitcnt vmcnt(0) lgkmcnt(0)")
     if (lane == 0) st(&s.A[x], SCANNED);
-    if (lane <= top) bit_clear(s, lane, x, levelmask);
+    if (lane <= top) bit_clear(s, lane, x, lcnt);
     uint64_t rest = w0 & ~(1ull << (x & 63));
     cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
     if (!list16 && cand >= 0) {
@@ -508,17 +496,30 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       int ccnt = ld(&lenv[cand]);
       cand_y = lane < ccnt ? (coh ? ld(&list[ce0 + lane]) : list[ce0 + lane]) : -1;
     }
+    SEG(2, "s_waitcnt lgkmcnt(0)")
     int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
     // the first chunk is handled in its own straight-line block so that no wait for the
     // prefetch in flight is placed in it
-    if (nw > 0) scan_entry(s, x, y, nw, e0 + lane, bound, levelmask, &bl, &by);
-    for (int base = 64; base < cnt; base += 64) {
-      int e = base + lane;
-      if (e >= cnt) break;
-      int y2 = list16 ? (int)list16[e0 + e] : (coh ? ld(&list[e0 + e]) : list[e0 + e]);
-      int nw2 = atomicAdd(&s.A[y2], 1) + 1;
-      if (nw2 > 0) scan_entry(s, x, y2, nw2, e0 + e, bound, levelmask, &bl, &by);
+    if (nw > 0) scan_entry(s, x, y, nw, e0 + lane, bound, lcnt, &bl, &by);
+    SEG(3, "s_waitcnt lgkmcnt(0)")
+    // longer lists: four chunks' loads are issued together, then processed in order
+    for (int base = 64; base < cnt; base += 256) {
+      int yv[4];
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        int e = base + 64 * k + lane;
+        yv[k] = e < cnt ? (list16 ? (int)list16[e0 + e] : (coh ? ld(&list[e0 + e]) : list[e0 + e])) : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        int e = base + 64 * k + lane;
+        if (e < cnt) {
+          int nw2 = atomicAdd(&s.A[yv[k]], 1) + 1;
+          if (nw2 > 0) scan_entry(s, x, yv[k], nw2, e0 + e, bound, lcnt, &bl, &by);
+        }
+      }
     }
+    SEG(4, "s_waitcnt lgkmcnt(0)")
     int M = wave_max_i(bl);
     int nx = -1;
     if (M > jx) {
@@ -529,8 +530,12 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       nx = m < cand ? m : cand;
     }
     x = nx;
+    SEG(5, "s_waitcnt lgkmcnt(0)")
   }
+#undef SEG
   if (prof_hits) *prof_hits += hits;
+  if (tm && lane == 0)
+    for (int k = 0; k < 6; k++) atomicAdd(&s.prof_cnt[k], tseg[k]);
   return steps;
 }
 
@@ -568,7 +573,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       // ---- round setup: keys, marks, bitmaps (levels 0..bound)
       int words = (bound + 1) * s.ls;
       for (int w = threadIdx.x; w < words; w += IB) st(&s.bits[w], (uint64_t)0);
-      if (threadIdx.x == 0) sh.levelmask = 0;
+      if (threadIdx.x < 64) sh.lcnt[threadIdx.x] = 0;
       for (int x = threadIdx.x; x < n; x += IB) {
         st(&s.A[x], 0);
         st(&s.B[x], x);
@@ -576,14 +581,14 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       mark_clear(s, total);
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
-        if (ld(&s.C[x]) == x) bit_set(s, 0, x, &sh.levelmask);
+        if (ld(&s.C[x]) == x) bit_set(s, 0, x, sh.lcnt);
       __syncthreads();
       // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
       const int32_t *stv = first ? s.R : s.E;
       if (threadIdx.x < 64) {
         unsigned long long hits = 0;
-        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, false, bound, &sh.levelmask, &hits)
-                      : scan_round(s, stv, s.D, s.lists, nullptr, true, bound, &sh.levelmask, &hits);
+        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, false, bound, sh.lcnt, &hits)
+                      : scan_round(s, stv, s.D, s.lists, nullptr, true, bound, sh.lcnt, &hits);
         if (s.pf && threadIdx.x == 0) {
           atomicAdd(&A.cnt[CNT_PH + 10], (unsigned long long)(r > 0 ? r : 0));
           atomicAdd(&A.cnt[CNT_PH + 11], hits);
@@ -761,6 +766,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   }
   long long steps = 0, rounds = 0;
   s.pf = A.prof == 1 || (A.prof == 2 && item_index == 0);
+  s.prof_cnt = A.cnt + CNT_PH + 16;
   unsigned long long pt = s.pf ? wall_clock64() : 0;
   // every item reads its rows at least once: vtx, rs, rd per vertex and one index per entry
   if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * n + 4LL * d.m));
