@@ -66,6 +66,9 @@ struct Workspace {
 };
 
 std::mutex g_lock;
+
+// device FrontCounts live in the counter block, after the 128 words used by the drivers
+FrontCounts *front_counts(Workspace &w) { return (FrontCounts *)(w.b[B_DCNT].as<unsigned long long>() + 128); }
 std::vector<Workspace *> g_ws;
 
 int get_ws(Workspace **out) {
@@ -120,14 +123,13 @@ int check_csr(const wcc_csr *g) {
   return WCC_OK;
 }
 
-// Front end shared by every entry point: buffers sized for N, grouping, compaction into
-// arena 0.  Outputs na (assigned vertices), K (clusters), E (intra entries).
-struct FrontOut {
-  int64_t na = 0, K = 0, E = 0;
-};
+// Front end shared by every entry point.  Buffers are sized for the worst case (every
+// vertex assigned, every entry intra-cluster), so no size has to be read back before the
+// compaction; the sizes it produced stay on the device in FrontCounts.
+int ensure_items(Workspace &w, int64_t cap, bool with_sets);
 
-int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate, bool want_ids,
-              FrontOut *fo, hipStream_t s) {
+int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate, bool want_ids, bool all_items,
+              hipStream_t s) {
   int64_t N = g->num_vertices;
   size_t n4 = (size_t)(N > 0 ? N : 1) * 4;
   for (int id : {B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_LOCV, B_DEGIN, B_CURSOR,
@@ -141,7 +143,13 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
   size_t tmpb = prim_radix_tmp_bytes(N > 0 ? N : 1);
   size_t sb = prim_scan_tmp_bytes(N > 0 ? N : 1);
   TRY(w.b[B_TMP].ensure(tmpb > sb ? tmpb : sb));
-  TRY(w.b[B_DCNT].ensure(128 * sizeof(unsigned long long)));
+  TRY(w.b[B_DCNT].ensure(256 * sizeof(unsigned long long)));
+  size_t e4 = (size_t)(g->num_entries > 0 ? g->num_entries : 1) * 4;
+  TRY(w.b[B_ADJ0].ensure(e4));
+  TRY(w.b[B_ADJ1].ensure(e4));
+  TRY(w.b[B_SEDGE].ensure(e4));
+  TRY(w.b[B_SMARK].ensure(e4 / 4 + 64));
+  TRY(ensure_items(w, N + 1, all_items));
 
   FrontBufs f;
   f.off = g->row_offsets;
@@ -169,16 +177,15 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
     TRY(front_validate(f, s, &ok));
     if (!ok) return WCC_EGRAPH;
   }
-  TRY(front_group(f, w.b[B_VTX0].as<int32_t>(), w.b[B_CLSTART].as<int64_t>(),
-                  want_ids ? w.b[B_CLIDS].as<int32_t>() : nullptr, &fo->na, &fo->K, s));
-  TRY(front_count(f, w.b[B_VTX0].as<int32_t>(), fo->na, w.b[B_RD0].as<int32_t>(), w.b[B_RS0].as<int64_t>(),
-                  &fo->E, s));
-  size_t e4 = (size_t)(fo->E > 0 ? fo->E : 1) * 4;
-  TRY(w.b[B_ADJ0].ensure(e4));
-  TRY(w.b[B_ADJ1].ensure(e4));
-  TRY(w.b[B_SEDGE].ensure(e4));
-  TRY(w.b[B_SMARK].ensure(e4 / 4 + 64));
-  TRY(front_fill(f, w.b[B_CLSTART].as<int64_t>(), w.b[B_RS0].as<int64_t>(), w.b[B_ADJ0].as<int32_t>(), s));
+  return front_build(f, front_counts(w), w.b[B_VTX0].as<int32_t>(), w.b[B_CLSTART].as<int64_t>(),
+                     want_ids ? w.b[B_CLIDS].as<int32_t>() : nullptr, w.b[B_RD0].as<int32_t>(),
+                     w.b[B_RS0].as<int64_t>(), w.b[B_ADJ0].as<int32_t>(), w.b[B_ITEMS0].as<ItemDesc>(),
+                     all_items ? w.b[B_SET0].as<int32_t>() : nullptr, all_items, s);
+}
+
+int read_counts(Workspace &w, FrontCounts *h, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(h, front_counts(w), sizeof(FrontCounts), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return WCC_OK;
 }
 
@@ -251,7 +258,7 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     A.out = out;
     A.out_count = dcount;
     if (base.split_only) A.split_set = set_sorted;
-    HIP_TRY(hipMemsetAsync(dcount, 0, 3 * sizeof(int32_t), s));
+    TRY(prim_fill32(dcount, 0u, 3, s));
     HIP_TRY(hipEventRecord(w.ev0, s));
     if (nbig > 0) {
       ItemArgs Bg = A;
@@ -362,26 +369,20 @@ int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, 
   TRY(get_ws(&wp));
   Workspace &w = *wp;
   HIP_TRY(hipEventRecord(w.ev0, s));
-  FrontOut fo;
-  TRY(run_front(w, g, mem_in, (p.flags & WCC_FLAG_VALIDATE) != 0, false, &fo, s));
+  TRY(run_front(w, g, mem_in, (p.flags & WCC_FLAG_VALIDATE) != 0, false, false, s));
   HIP_TRY(hipEventRecord(w.ev1, s));
-  HIP_TRY(hipEventSynchronize(w.ev1));
+  TRY(prim_fill32(w.b[B_ACC].p, 0xffffffffu, N, s));
+  unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  TRY(prim_fill32(cnt, 0u, 2 * CNT_NUM, s));
+  FrontCounts fc;
+  TRY(read_counts(w, &fc, s));
   float fms = 0;
   HIP_TRY(hipEventElapsedTime(&fms, w.ev0, w.ev1));
   st.ms_front = fms;
-  st.clusters = fo.K;
-  st.intra_entries = fo.E;
-  TRY(ensure_items(w, fo.na + 1, false));
-  int32_t *dnitems = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 20);
-  TRY(front_items(w.b[B_CLSTART].as<int64_t>(), fo.K, fo.na, w.b[B_RS0].as<int64_t>(), fo.E,
-                  w.b[B_ITEMS0].as<ItemDesc>(), dnitems, s));
-  HIP_TRY(hipMemsetAsync(w.b[B_ACC].p, 0xff, (size_t)N * 4, s));
-  unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
-  HIP_TRY(hipMemsetAsync(cnt, 0, CNT_NUM * sizeof(unsigned long long), s));
-  int32_t nitems = 0;
-  HIP_TRY(hipMemcpyAsync(&nitems, dnitems, sizeof(nitems), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  ItemArgs A = base_args(w, p, (int32_t)(fo.na + 1));
+  st.clusters = fc.K;
+  st.intra_entries = fc.E;
+  int32_t nitems = fc.nitems;
+  ItemArgs A = base_args(w, p, (int32_t)(N + 1));
   A.rec = rec;
   A.rec_cap = rec_cap;
   A.prof = env_int("WCC_PROF", 0);
@@ -427,14 +428,15 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   Workspace &w = *wp;
   int64_t N = g->num_vertices;
   TRY(w.b[B_SPLITMEM].ensure((size_t)(N > 0 ? N : 1) * 4));
-  TRY(w.b[B_DCNT].ensure(128 * sizeof(unsigned long long)));
-  HIP_TRY(hipMemsetAsync(lambdas, 0, (size_t)num_sets * 4, s));
-  if (nv > 0) HIP_TRY(hipMemsetAsync(sides, 0, (size_t)nv, s));
+  TRY(w.b[B_DCNT].ensure(256 * sizeof(unsigned long long)));
+  TRY(prim_fill32(lambdas, 0u, num_sets, s));
   if (nv == 0) {
     HIP_TRY(hipStreamSynchronize(s));
     return WCC_OK;
   }
   if (!verts || !sides) return WCC_EINVAL;
+  TRY(prim_fill32(sides, 0u, nv / 4, s));
+  if (nv % 4) HIP_TRY(hipMemcpyAsync(sides + (nv / 4) * 4, "\0\0\0", (size_t)(nv % 4), hipMemcpyHostToDevice, s));
   int32_t *mem = w.b[B_SPLITMEM].as<int32_t>();
   unsigned long long *bad = w.b[B_DCNT].as<unsigned long long>() + 100;
   TRY(front_split_membership(verts, set_offsets, num_sets, nv, N, mem, bad, s));
@@ -442,16 +444,14 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (hb) return WCC_EINVAL;
-  FrontOut fo;
-  TRY(run_front(w, g, mem, false, true, &fo, s));
-  TRY(ensure_items(w, fo.K + 1, true));
-  TRY(front_split_items(w.b[B_CLSTART].as<int64_t>(), w.b[B_CLIDS].as<int32_t>(), fo.K, fo.na,
-                        w.b[B_RS0].as<int64_t>(), fo.E, w.b[B_ITEMS0].as<ItemDesc>(), w.b[B_SET0].as<int32_t>(), s));
+  TRY(run_front(w, g, mem, false, true, true, s));
+  FrontCounts fc;
+  TRY(read_counts(w, &fc, s));
   wcc_params p;
   wcc_default_params(&p);
-  ItemArgs A = base_args(w, p, (int32_t)(fo.K + 1));
+  ItemArgs A = base_args(w, p, (int32_t)(fc.K + 1));
   unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
-  HIP_TRY(hipMemsetAsync(cnt, 0, CNT_NUM * sizeof(unsigned long long), s));
+  TRY(prim_fill32(cnt, 0u, 2 * CNT_NUM, s));
   A.split_only = 1;
   A.split_lambda = lambdas;
   A.split_side = sides;
@@ -460,7 +460,7 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   int64_t lv;
   double ms;
   int64_t launches;
-  TRY(run_levels(w, A, (int32_t)fo.K, WCC_CRIT_LOG10, p, &lv, &ms, &launches, s));
+  TRY(run_levels(w, A, (int32_t)fc.K, WCC_CRIT_LOG10, p, &lv, &ms, &launches, s));
   HIP_TRY(hipStreamSynchronize(s));
   return WCC_OK;
 }
@@ -568,8 +568,9 @@ int wcc_cluster_csr(const wcc_csr *g, const int32_t *membership_in, int64_t *ncl
     Workspace *wp;
     TRY(get_ws(&wp));
     Workspace &w = *wp;
-    FrontOut fo;
-    TRY(run_front(w, g, membership_in, false, true, &fo, s));
+    TRY(run_front(w, g, membership_in, false, true, false, s));
+    FrontCounts fo;
+    TRY(read_counts(w, &fo, s));
     *nclusters = fo.K;
     *nassigned = fo.na;
     *nentries = fo.E;

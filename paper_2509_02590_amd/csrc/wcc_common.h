@@ -267,5 +267,6 @@ int prim_excl_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tota
 size_t prim_scan_tmp_bytes(int64_t n);
 int prim_radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                           int64_t n, int bits, void *tmp, size_t tmp_bytes, hipStream_t s,
-                          int *result_in_alt);
+                          int *result_in_alt, const int32_t *maxkey_m1 = nullptr);
+int prim_fill32(void *p, uint32_t v, int64_t nwords, hipStream_t s);
 size_t prim_radix_tmp_bytes(int64_t n);

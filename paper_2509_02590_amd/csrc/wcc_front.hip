@@ -99,7 +99,10 @@ __global__ void __launch_bounds__(FB) k_validate_entries(const OT *off, const in
 }
 
 // ---------------------------------------------------------------- grouping
-__global__ void k_member_stats(const int32_t *mem, int64_t N, int32_t *maxid, unsigned long long *na) {
+// Every size the front end produces (assigned vertices na, clusters K, intra entries E,
+// initial items) stays in device counters (FrontCounts), so the whole front end runs
+// without a host synchronisation and can be captured in a graph.
+__global__ void k_member_stats(const int32_t *mem, int64_t N, FrontCounts *fc) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t m = -1;
   int c = 0;
@@ -126,31 +129,34 @@ __global__ void k_member_stats(const int32_t *mem, int64_t N, int32_t *maxid, un
       ts += ws[w];
       tm = wm[w] > tm ? wm[w] : tm;
     }
-    if (ts) atomicAdd(na, (unsigned long long)ts);
-    if (tm >= 0) atomicMax(maxid, tm);
+    if (ts) atomicAdd((unsigned long long *)&fc->na, (unsigned long long)ts);
+    if (tm >= 0) atomicMax(&fc->maxid, tm);
   }
 }
 
-__global__ void k_sort_init(const int32_t *mem, int64_t N, uint32_t unassigned_key, uint32_t *keys,
+// unassigned vertices get key maxid + 1, so they sort after every cluster
+__global__ void k_sort_init(const int32_t *mem, int64_t N, const FrontCounts *fc, uint32_t *keys,
                             uint32_t *vals) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   int32_t m = mem[i];
-  keys[i] = m >= 0 ? (uint32_t)m : unassigned_key;
+  keys[i] = m >= 0 ? (uint32_t)m : (uint32_t)(fc->maxid + 1);
   vals[i] = (uint32_t)i;
 }
 
-__global__ void k_cluster_flags(const uint32_t *keys, int64_t na, int32_t *flag) {
+__global__ void k_cluster_flags(const uint32_t *keys, int64_t N, const FrontCounts *fc, int32_t *flag) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= na) return;
-  flag[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0;
+  if (p >= N) return;
+  int64_t na = fc->na;
+  flag[p] = (p < na && (p == 0 || keys[p] != keys[p - 1])) ? 1 : 0;
 }
 
 // cid = exclusive-scan(flag) + flag - 1 ; record cluster starts and per-vertex tables
 __global__ void k_cluster_tables(const uint32_t *keys, const uint32_t *vals, const int32_t *flag,
-                                 const int32_t *flag_scan, int64_t na, int64_t *cl_start,
-                                 int32_t *cl_ids, int32_t *cidv, int32_t *locv, int32_t *vtx0) {
+                                 const int32_t *flag_scan, int64_t N, const FrontCounts *fc,
+                                 int64_t *cl_start, int32_t *cl_ids, int32_t *cidv, int32_t *vtx0) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t na = fc->na;
   if (p >= na) return;
   int32_t c = flag_scan[p] + flag[p] - 1;
   uint32_t v = vals[p];
@@ -158,14 +164,15 @@ __global__ void k_cluster_tables(const uint32_t *keys, const uint32_t *vals, con
     cl_start[c] = p;
     if (cl_ids) cl_ids[c] = (int32_t)keys[p];
   }
+  if (p == na - 1) cl_start[c + 1] = na;
   cidv[v] = c;
   vtx0[p] = (int32_t)v;
 }
 
 __global__ void k_cluster_locals(const int32_t *vtx0, const int32_t *cidv, const int64_t *cl_start,
-                                 int64_t na, int32_t *locv) {
+                                 const FrontCounts *fc, int32_t *locv) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= na) return;
+  if (p >= fc->na) return;
   int32_t v = vtx0[p];
   locv[v] = (int32_t)(p - cl_start[cidv[v]]);
 }
@@ -203,11 +210,11 @@ __global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t
       if (cnt[i]) atomicAdd(&deg_in[r0 + i], cnt[i]);
 }
 
-__global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t na, int32_t *rd0,
-                             int64_t *rs0) {
+__global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t N, const FrontCounts *fc,
+                             int32_t *rd0, int64_t *rs0) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= na) return;
-  int32_t d = deg_in[vtx0[p]];
+  if (p >= N) return;
+  int32_t d = p < fc->na ? deg_in[vtx0[p]] : 0;
   rd0[p] = d;
   rs0[p] = d;
 }
@@ -275,25 +282,29 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
     if (val[i] >= 0) adj0[cache[row[i]] + slot[i]] = val[i];
 }
 
-__global__ void k_make_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0,
-                             int64_t E, ItemDesc *items, int32_t *nitems) {
+__global__ void k_make_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t N, const FrontCounts *fc,
+                             const int64_t *rs0, ItemDesc *items, int32_t *item_set, bool all) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t K = fc->K, na = fc->na, E = fc->E;
   if (c >= K) return;
   int64_t b = cl_start[c];
-  int64_t e = c + 1 < K ? cl_start[c + 1] : na;
+  int64_t e = cl_start[c + 1];
   int64_t eb = rs0[b];
   int64_t ee = e < na ? rs0[e] : E;
-  if (ee == eb) return;  // Alg. 1: clusters without induced edges are not refined
+  if (!all && ee == eb) return;  // Alg. 1: clusters without induced edges are not refined
   ItemDesc d;
   d.b = (int32_t)b;
   d.n = (int32_t)(e - b);
   d.eb = eb;
   d.m = ee - eb;
   d.depth = 0;
-  d.flags = ITEM_CCR;
-  int32_t slot = atomicAdd(nitems, 1);
+  d.flags = all ? 0 : ITEM_CCR;
+  int32_t slot = all ? (int32_t)c : atomicAdd((int32_t *)&fc->nitems, 1);
   items[slot] = d;
+  if (item_set) item_set[slot] = cl_ids ? cl_ids[c] : (int32_t)c;
 }
+
+__global__ void k_finish_counts(FrontCounts *fc) { fc->K = fc->K32; }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -301,7 +312,8 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------- host wrappers
 int front_validate(const FrontBufs &f, hipStream_t s, int *ok) {
-  HIP_TRY(hipMemsetAsync(f.dcnt, 0, 4 * sizeof(unsigned long long), s));
+  int rc0 = prim_fill32(f.dcnt, 0u, 8, s);
+  if (rc0) return rc0;
   unsigned gb = nblk(f.N + 1, FB), ge = nblk(f.nnz, FTILE);
   if (f.obits == 32) {
     hipLaunchKernelGGL(k_validate_offsets<int32_t>, dim3(gb), dim3(FB), 0, s, (const int32_t *)f.off,
@@ -332,62 +344,40 @@ int front_validate(const FrontBufs &f, hipStream_t s, int *ok) {
   return WCC_OK;
 }
 
-// Groups vertices by cluster.  Outputs: *na assigned vertices, *K clusters, vtx0[na]
-// (global ids, cluster-major ascending), cl_start[K+1], cl_ids[K] (nullable), per-vertex
-// cidv/locv (cidv = -1 for unassigned).
-int front_group(const FrontBufs &f, int32_t *vtx0, int64_t *cl_start, int32_t *cl_ids, int64_t *na_out,
-                int64_t *K_out, hipStream_t s) {
+// Groups vertices by cluster and compacts every cluster's induced subgraph into arena 0:
+// vtx0 (global ids, cluster-major, ascending inside a cluster), cl_start (K+1), cl_ids
+// (nullable), rd0/rs0 (row lengths and starts), adj0 (local ids) and the initial items
+// (clusters with at least one induced edge; with all_items, every cluster in order and
+// item_set[i] = i).  Sizes end in *fc; nothing is read back to the host.
+int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_start, int32_t *cl_ids,
+                int32_t *rd0, int64_t *rs0, int32_t *adj0, ItemDesc *items, int32_t *item_set, bool all_items,
+                hipStream_t s) {
   int64_t N = f.N;
-  HIP_TRY(hipMemsetAsync(f.dcnt, 0, sizeof(unsigned long long), s));
-  HIP_TRY(hipMemsetAsync(f.dmax, 0xff, sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_member_stats, dim3(nblk(N, 1024)), dim3(1024), 0, s, f.mem, N, f.dmax, f.dcnt);
-  HIP_TRY(hipGetLastError());
-  unsigned long long na = 0;
-  int32_t maxid = -1;
-  HIP_TRY(hipMemcpyAsync(&na, f.dcnt, sizeof(na), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&maxid, f.dmax, sizeof(maxid), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *na_out = (int64_t)na;
-  HIP_TRY(hipMemsetAsync(f.cidv, 0xff, (size_t)N * sizeof(int32_t), s));
-  if (na == 0) {
-    *K_out = 0;
-    HIP_TRY(hipMemsetAsync(cl_start, 0, sizeof(int64_t), s));
-    return WCC_OK;
-  }
-  int bits = 0;
-  while (bits < 32 && ((uint64_t)maxid + 1) >> bits) bits++;  // bit length of maxid + 1
-  uint32_t unassigned = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1);
-  hipLaunchKernelGGL(k_sort_init, dim3(nblk(N, 256)), dim3(256), 0, s, f.mem, N, unassigned, f.keys,
-                     f.vals);
+  int rc;
+  if ((rc = prim_fill32(fc, 0u, (int64_t)(sizeof(FrontCounts) / 4), s))) return rc;
+  if ((rc = prim_fill32(&fc->maxid, 0xffffffffu, 1, s))) return rc;
+  if ((rc = prim_fill32(f.cidv, 0xffffffffu, N, s))) return rc;
+  if ((rc = prim_fill32(cl_start, 0u, 2, s))) return rc;
+  if (N > 0) hipLaunchKernelGGL(k_member_stats, dim3(nblk(N, 1024)), dim3(1024), 0, s, f.mem, N, fc);
+  hipLaunchKernelGGL(k_sort_init, dim3(nblk(N, 256)), dim3(256), 0, s, f.mem, N, (const FrontCounts *)fc,
+                     f.keys, f.vals);
   HIP_TRY(hipGetLastError());
   int alt = 0;
-  int rc = prim_radix_sort_pairs(f.keys, f.vals, f.keys2, f.vals2, N, bits, f.tmp, f.tmp_bytes, s, &alt);
+  // four 8-bit passes; the passes above the key range copy through (decided on the device)
+  rc = prim_radix_sort_pairs(f.keys, f.vals, f.keys2, f.vals2, N, 32, f.tmp, f.tmp_bytes, s, &alt, &fc->maxid);
   if (rc) return rc;
   const uint32_t *keys = alt ? f.keys2 : f.keys;
   const uint32_t *vals = alt ? f.vals2 : f.vals;
-  hipLaunchKernelGGL(k_cluster_flags, dim3(nblk(na, 256)), dim3(256), 0, s, keys, (int64_t)na, f.flag);
-  int32_t *Kdev = (int32_t *)(f.dcnt + 1);
-  rc = prim_excl_scan_i32(f.flag, f.flag_scan, (int64_t)na, Kdev, f.tmp, f.tmp_bytes, s);
+  hipLaunchKernelGGL(k_cluster_flags, dim3(nblk(N, 256)), dim3(256), 0, s, keys, N, (const FrontCounts *)fc, f.flag);
+  rc = prim_excl_scan_i32(f.flag, f.flag_scan, N, &fc->K32, f.tmp, f.tmp_bytes, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_cluster_tables, dim3(nblk(na, 256)), dim3(256), 0, s, keys, vals, f.flag,
-                     f.flag_scan, (int64_t)na, cl_start, cl_ids, f.cidv, f.locv, vtx0);
-  hipLaunchKernelGGL(k_cluster_locals, dim3(nblk(na, 256)), dim3(256), 0, s, vtx0, f.cidv, cl_start,
-                     (int64_t)na, f.locv);
+  hipLaunchKernelGGL(k_cluster_tables, dim3(nblk(N, 256)), dim3(256), 0, s, keys, vals, f.flag, f.flag_scan, N,
+                     (const FrontCounts *)fc, cl_start, cl_ids, f.cidv, vtx0);
+  hipLaunchKernelGGL(k_cluster_locals, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, f.cidv, cl_start,
+                     (const FrontCounts *)fc, f.locv);
   HIP_TRY(hipGetLastError());
-  int32_t K = 0;
-  HIP_TRY(hipMemcpyAsync(&K, Kdev, sizeof(K), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  int64_t na64 = (int64_t)na;
-  HIP_TRY(hipMemcpyAsync(cl_start + K, &na64, sizeof(int64_t), hipMemcpyHostToDevice, s));
-  *K_out = K;
-  return WCC_OK;
-}
-
-// Counting pass of the compaction: rd0[p] (intra degree of position p) and rs0[p]
-// (exclusive prefix); *E_out = total intra entries.
-int front_count(const FrontBufs &f, const int32_t *vtx0, int64_t na, int32_t *rd0, int64_t *rs0,
-                int64_t *E_out, hipStream_t s) {
-  HIP_TRY(hipMemsetAsync(f.deg_in, 0, (size_t)f.N * sizeof(int32_t), s));
+  // counting pass: intra degree per vertex, then row starts by position
+  if ((rc = prim_fill32(f.deg_in, 0u, N, s))) return rc;
   if (f.nnz > 0) {
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
@@ -396,27 +386,15 @@ int front_count(const FrontBufs &f, const int32_t *vtx0, int64_t na, int32_t *rd
     else
       hipLaunchKernelGGL(k_count_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
                          f.N, f.nnz, f.cidv, f.deg_in);
-    HIP_TRY(hipGetLastError());
   }
-  if (na == 0) {
-    *E_out = 0;
-    return WCC_OK;
-  }
-  hipLaunchKernelGGL(k_gather_deg, dim3(nblk(na, 256)), dim3(256), 0, s, vtx0, f.deg_in, na, rd0, rs0);
+  hipLaunchKernelGGL(k_gather_deg, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, f.deg_in, N,
+                     (const FrontCounts *)fc, rd0, rs0);
   HIP_TRY(hipGetLastError());
-  int64_t *Edev = (int64_t *)(f.dcnt + 2);
-  int rc = prim_excl_scan_i64(rs0, rs0, na, Edev, f.tmp, f.tmp_bytes, s);
+  rc = prim_excl_scan_i64(rs0, rs0, N, &fc->E, f.tmp, f.tmp_bytes, s);
   if (rc) return rc;
-  int64_t E = 0;
-  HIP_TRY(hipMemcpyAsync(&E, Edev, sizeof(E), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *E_out = E;
-  return WCC_OK;
-}
-
-// Fill pass of the compaction into adj0 (E entries).
-int front_fill(const FrontBufs &f, const int64_t *cl_start, const int64_t *rs0, int32_t *adj0, hipStream_t s) {
-  HIP_TRY(hipMemsetAsync(f.cursor, 0, (size_t)f.N * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(1), 0, s, fc);
+  // fill pass
+  if ((rc = prim_fill32(f.cursor, 0u, N, s))) return rc;
   if (f.nnz > 0) {
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
@@ -425,17 +403,10 @@ int front_fill(const FrontBufs &f, const int64_t *cl_start, const int64_t *rs0, 
     else
       hipLaunchKernelGGL(k_fill_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
                          f.N, f.nnz, f.cidv, f.locv, cl_start, rs0, f.cursor, adj0);
-    HIP_TRY(hipGetLastError());
   }
-  return WCC_OK;
-}
-
-int front_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0, int64_t E,
-                ItemDesc *items, int32_t *nitems_dev, hipStream_t s) {
-  HIP_TRY(hipMemsetAsync(nitems_dev, 0, sizeof(int32_t), s));
-  if (K > 0)
-    hipLaunchKernelGGL(k_make_items, dim3(nblk(K, 256)), dim3(256), 0, s, cl_start, K, na, rs0, E, items,
-                       nitems_dev);
+  if (items)
+    hipLaunchKernelGGL(k_make_items, dim3(nblk(N, 256)), dim3(256), 0, s, cl_start, (const int32_t *)cl_ids, N,
+                       (const FrontCounts *)fc, rs0, items, item_set, all_items);
   HIP_TRY(hipGetLastError());
   return WCC_OK;
 }
@@ -467,31 +438,13 @@ __global__ void k_split_membership(const int32_t *verts, const int64_t *so, int3
   if (atomicCAS(&mem[v], -1, (int32_t)lo) != -1) atomicAdd(bad, 1ull);
 }
 
-__global__ void k_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K, int64_t na,
-                              const int64_t *rs0, int64_t E, ItemDesc *items, int32_t *item_set) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= K) return;
-  int64_t b = cl_start[c];
-  int64_t e = c + 1 < K ? cl_start[c + 1] : na;
-  int64_t eb = rs0[b];
-  int64_t ee = e < na ? rs0[e] : E;
-  ItemDesc d;
-  d.b = (int32_t)b;
-  d.n = (int32_t)(e - b);
-  d.eb = eb;
-  d.m = ee - eb;
-  d.depth = 0;
-  d.flags = 0;
-  items[c] = d;
-  item_set[c] = cl_ids[c];
-}
-
 }  // namespace
 
 int front_split_membership(const int32_t *verts, const int64_t *set_offsets, int32_t num_sets, int64_t nv,
                            int64_t N, int32_t *mem, unsigned long long *bad, hipStream_t s) {
-  HIP_TRY(hipMemsetAsync(mem, 0xff, (size_t)(N > 0 ? N : 1) * 4, s));
-  HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned long long), s));
+  int rc;
+  if ((rc = prim_fill32(mem, 0xffffffffu, N, s))) return rc;
+  if ((rc = prim_fill32(bad, 0u, 2, s))) return rc;
   int64_t work = nv > num_sets ? nv : num_sets;
   if (work > 0)
     hipLaunchKernelGGL(k_split_membership, dim3(nblk(work, 256)), dim3(256), 0, s, verts, set_offsets, num_sets,
@@ -500,11 +453,3 @@ int front_split_membership(const int32_t *verts, const int64_t *set_offsets, int
   return WCC_OK;
 }
 
-int front_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K, int64_t na, const int64_t *rs0,
-                      int64_t E, ItemDesc *items, int32_t *item_set, hipStream_t s) {
-  if (K > 0)
-    hipLaunchKernelGGL(k_split_items, dim3(nblk(K, 256)), dim3(256), 0, s, cl_start, cl_ids, K, na, rs0, E, items,
-                       item_set);
-  HIP_TRY(hipGetLastError());
-  return WCC_OK;
-}

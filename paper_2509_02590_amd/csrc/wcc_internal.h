@@ -19,19 +19,24 @@ struct FrontBufs {
   int32_t *dmax;
 };
 
+// Device-resident sizes produced by the front end.
+struct FrontCounts {
+  int64_t na;      // vertices with a cluster
+  int64_t K;       // clusters
+  int64_t E;       // directed entries of all induced cluster subgraphs
+  int32_t K32;     // cluster count as written by the scan
+  int32_t maxid;   // largest cluster id, -1 if none
+  int32_t nitems;  // initial items
+  int32_t pad[3];
+};
+
 // wcc_front.hip
 int front_validate(const FrontBufs &f, hipStream_t s, int *ok);
-int front_group(const FrontBufs &f, int32_t *vtx0, int64_t *cl_start, int32_t *cl_ids, int64_t *na_out,
-                int64_t *K_out, hipStream_t s);
-int front_count(const FrontBufs &f, const int32_t *vtx0, int64_t na, int32_t *rd0, int64_t *rs0,
-                int64_t *E_out, hipStream_t s);
-int front_fill(const FrontBufs &f, const int64_t *cl_start, const int64_t *rs0, int32_t *adj0, hipStream_t s);
-int front_items(const int64_t *cl_start, int64_t K, int64_t na, const int64_t *rs0, int64_t E,
-                ItemDesc *items, int32_t *nitems_dev, hipStream_t s);
+int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_start, int32_t *cl_ids,
+                int32_t *rd0, int64_t *rs0, int32_t *adj0, ItemDesc *items, int32_t *item_set, bool all_items,
+                hipStream_t s);
 int front_split_membership(const int32_t *verts, const int64_t *set_offsets, int32_t num_sets, int64_t nv,
                            int64_t N, int32_t *mem, unsigned long long *bad, hipStream_t s);
-int front_split_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t K, int64_t na, const int64_t *rs0,
-                      int64_t E, ItemDesc *items, int32_t *item_set, hipStream_t s);
 
 // wcc_items.hip
 int items_block();

@@ -976,7 +976,8 @@ int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t 
                     uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
                     hipStream_t s, int small_max, int32_t *nbig) {
   if (n <= 0) return WCC_OK;
-  HIP_TRY(hipMemsetAsync(nbig, 0, sizeof(int32_t), s));
+  int rc0 = prim_fill32(nbig, 0u, 1, s);
+  if (rc0) return rc0;
   hipLaunchKernelGGL(k_item_keys, dim3((n + 255) / 256), dim3(256), 0, s, in, n, k1, v1, small_max, nbig);
   HIP_TRY(hipGetLastError());
   int bits = 31, alt = 0;

@@ -116,7 +116,8 @@ int excl_scan(const T *in, T *out, int64_t n, T *total_dev, void *tmp, size_t tm
     hipLaunchKernelGGL(k_tile_reduce<T>, dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, n,
                        partial);
   } else {
-    HIP_TRY(hipMemsetAsync(partial, 0, sizeof(T), s));
+    int rc = prim_fill32(partial, 0u, (int64_t)(sizeof(T) / 4), s);
+    if (rc) return rc;
   }
   hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(SCAN_BLOCK), 0, s, partial, tiles,
                      total_dev);
@@ -132,9 +133,17 @@ constexpr int RS_BLOCK = 256;
 constexpr int RS_ITERS = 8;
 constexpr int RS_TILE = RS_BLOCK * RS_ITERS;
 
+// A pass is inactive when a device-side maximum key is given and has no bits at `shift`;
+// an inactive pass copies its input to its output so the buffer parity is unchanged.
+DEV bool pass_active(const int32_t *maxkey_m1, int shift) {
+  return !maxkey_m1 || ((uint32_t)(*maxkey_m1 + 1) >> shift) != 0;
+}
+
 __global__ void __launch_bounds__(RS_BLOCK) k_radix_hist(const uint32_t *keys, int64_t n,
                                                          int shift, uint32_t mask,
-                                                         int32_t *hist, int ntiles) {
+                                                         int32_t *hist, int ntiles,
+                                                         const int32_t *maxkey_m1) {
+  if (!pass_active(maxkey_m1, shift)) return;
   __shared__ int cnt[256];
   for (int d = threadIdx.x; d < 256; d += RS_BLOCK) cnt[d] = 0;
   __syncthreads();
@@ -150,8 +159,18 @@ __global__ void __launch_bounds__(RS_BLOCK) k_radix_hist(const uint32_t *keys, i
 __global__ void __launch_bounds__(RS_BLOCK) k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
                                                             uint32_t *kout, uint32_t *vout,
                                                             int64_t n, int shift, int nbits,
-                                                            const int32_t *offs, int ntiles) {
+                                                            const int32_t *offs, int ntiles,
+                                                            const int32_t *maxkey_m1) {
   constexpr int NW = RS_BLOCK / 64;
+  if (!pass_active(maxkey_m1, shift)) {
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = threadIdx.x; i < RS_TILE; i += RS_BLOCK)
+      if (base + i < n) {
+        kout[base + i] = kin[base + i];
+        vout[base + i] = vin[base + i];
+      }
+    return;
+  }
   __shared__ int run[256];
   __shared__ int wcnt[NW][256];
   uint32_t mask = (1u << nbits) - 1;
@@ -194,7 +213,22 @@ __global__ void __launch_bounds__(RS_BLOCK) k_radix_scatter(const uint32_t *kin,
   }
 }
 
+__global__ void k_fill32(uint32_t *p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 }  // namespace
+
+// Fills nwords 32-bit words with v (a kernel, so that it can be captured in a graph).
+int prim_fill32(void *p, uint32_t v, int64_t nwords, hipStream_t s) {
+  if (nwords <= 0) return WCC_OK;
+  int64_t blocks = (nwords + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, v, nwords);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
 
 size_t prim_scan_tmp_bytes(int64_t n) {
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -222,7 +256,7 @@ size_t prim_radix_tmp_bytes(int64_t n) {
 // (keys, vals) or in the alternates (*result_in_alt = 1).
 int prim_radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
                           int64_t n, int bits, void *tmp, size_t tmp_bytes, hipStream_t s,
-                          int *result_in_alt) {
+                          int *result_in_alt, const int32_t *maxkey_m1) {
   *result_in_alt = 0;
   if (n <= 1 || bits <= 0) return WCC_OK;
   if (tmp_bytes < prim_radix_tmp_bytes(n)) return WCC_EINVAL;
@@ -237,11 +271,11 @@ int prim_radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, ui
     uint32_t mask = (1u << nb) - 1;
     int64_t hn = (int64_t)(mask + 1) * ntiles;
     hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(RS_BLOCK), 0, s, (const uint32_t *)ki, n,
-                       shift, mask, hist, ntiles);
+                       shift, mask, hist, ntiles, maxkey_m1);
     int rc = prim_excl_scan_i32(hist, offs, hn, nullptr, stmp, stmp_bytes, s);
     if (rc) return rc;
     hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(RS_BLOCK), 0, s, (const uint32_t *)ki,
-                       (const uint32_t *)vi, ko, vo, n, shift, nb, (const int32_t *)offs, ntiles);
+                       (const uint32_t *)vi, ko, vo, n, shift, nb, (const int32_t *)offs, ntiles, maxkey_m1);
     HIP_TRY(hipGetLastError());
     uint32_t *t = ki;
     ki = ko;
