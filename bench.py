@@ -5,7 +5,11 @@ final relabel) over the 1M-vertex / 20M-edge Chung-Lu workload with a planted po
 clustering (input already resident in HBM).  Prints ONE JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2]
-                  [--exec plain|batched] [--mode kcore|paper] [--no-cpu-baseline]
+                  [--exec batched|plain] [--no-compare] [--mode kcore|paper] [--no-cpu-baseline]
+
+The timed form (default batched: device-driven level launches replayed from a HIP
+graph) gives `value`; the other form is timed after it on the same input and reported in
+`other_exec` together with whether both produced the same membership.
 """
 import argparse
 import json
@@ -51,7 +55,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1")
-    ap.add_argument("--exec", dest="exec_mode", default="plain")
+    ap.add_argument("--exec", dest="exec_mode", default="batched")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="skip timing the other execution form")
     ap.add_argument("--mode", default="kcore")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-bytes", type=float, default=None,
@@ -76,26 +82,38 @@ def main():
     idx = torch.from_numpy(g.indices).to(dev)
     mem = torch.from_numpy(g.membership).to(dev)
     out = torch.empty_like(mem)
-    kw = dict(s_pre=10, s_post=10, mode=args.mode, exec_mode=args.exec_mode)
     torch.cuda.synchronize()
 
-    for i in range(args.warmup):
-        wcc.wcc_run(off, idx, mem, out=out, **kw)
-        log("warmup %d done" % i)
-    torch.cuda.synchronize()
-    stats = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        _, st, _ = wcc.wcc_run(off, idx, mem, out=out, **kw)
-        stats.append(st.as_dict())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    def timed(exec_mode):
+        kw = dict(s_pre=10, s_post=10, mode=args.mode, exec_mode=exec_mode)
+        for i in range(args.warmup):
+            wcc.wcc_run(off, idx, mem, out=out, **kw)
+            log("%s warmup %d done" % (exec_mode, i))
+        torch.cuda.synchronize()
+        stats = []
+        t_start = time.perf_counter()
+        for i in range(args.steps):
+            _, st, _ = wcc.wcc_run(off, idx, mem, out=out, **kw)
+            stats.append(st.as_dict())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        log("%s: timed %d steps: %.2f ms/step, %.3e edges/s"
+            % (exec_mode, args.steps, 1000.0 * elapsed / args.steps, g.m * args.steps / elapsed))
+        return elapsed, stats, out.clone()
+
+    elapsed, stats, res = timed(args.exec_mode)
     ms_step = 1000.0 * elapsed / args.steps
     value = g.m / (elapsed / args.steps)
-    log("timed %d steps: %.2f ms/step, %.3e edges/s" % (args.steps, ms_step, value))
+    other = None
+    if args.compare:
+        other_mode = "plain" if args.exec_mode == "batched" else "batched"
+        o_elapsed, o_stats, o_res = timed(other_mode)
+        other = {"exec": other_mode, "value": g.m / (o_elapsed / args.steps),
+                 "ms_per_step": 1000.0 * o_elapsed / args.steps,
+                 "equal_output": bool(torch.equal(res, o_res))}
 
     # roofline of the dominant kernel (the per-item kernel), timed with HIP events that
-    # the library records around every item launch on the caller's stream
+    # the library records around every item launch on the stream it is launched on
     s0 = stats[-1]
     launches = max(s0["item_launches"], 1)
     avg_launch_s = s0["ms_item_kernel"] / 1000.0 / launches
@@ -104,10 +122,12 @@ def main():
     traffic = args.traffic_bytes
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_items", "avg_launch_ms": avg_launch_s * 1e3,
+                "kernel": "k_items",
+                "avg_launch_ms": avg_launch_s * 1e3,
                 "alg_bytes_per_launch": alg_bytes_per_launch, "launches_per_step": s0["item_launches"]}
 
-    # whole-job floor: one pass over the input (SURVEY-style B_floor), for context
+    # whole-job floor: one pass over the input (index + neighbour-cluster gather per entry,
+    # offsets + membership + output per vertex), for context
     b_floor = g.indices.shape[0] * 8 + g.n * (4 + 4 + 4)
     line = {
         "metric": METRIC,
@@ -129,8 +149,11 @@ def main():
         "roofline": roofline,
         "floor_gbs": b_floor / (elapsed / args.steps) / 1e9,
         "step_stats": {k: s0[k] for k in ("items", "mincuts", "accepted", "levels", "scan_steps",
-                                           "scan_rounds", "ms_front", "ms_items", "ms_item_kernel")},
+                                           "scan_rounds", "ms_front", "ms_items", "ms_item_kernel",
+                                           "graph_replays")},
     }
+    if other is not None:
+        line["other_exec"] = other
     if not args.no_cpu_baseline:
         try:
             threads = min(16, len(os.sched_getaffinity(0)))

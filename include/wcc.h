@@ -81,10 +81,17 @@ typedef struct {
                              k(n)-core (larger than s_post) whenever that core is not the
                              whole set; only whole-core sets are cut */
 
-#define WCC_EXEC_PLAIN 0   /* level-synchronous: one launch per recursion depth */
-#define WCC_EXEC_BATCHED 1 /* persistent work-queue kernel, one launch per job */
+#define WCC_EXEC_PLAIN 0   /* level-synchronous: per recursion depth, one launch for each
+                              size bin, the host reading the child count in between */
+#define WCC_EXEC_BATCHED 1 /* device-driven: per recursion depth one launch for each size
+                              bin whose item count is read on the device; children go
+                              straight into the next depth's size-bin lists, the host does
+                              not synchronise inside a run, and the whole call is recorded
+                              as a HIP graph and replayed when called again with the same
+                              buffers and parameters */
 
 #define WCC_FLAG_VALIDATE 1u /* check the CSR first; WCC_EGRAPH if malformed */
+#define WCC_FLAG_NO_GRAPH 2u /* BATCHED: neither record nor replay a HIP graph */
 
 typedef struct {
   int32_t criterion;   /* WCC_CRIT_* (default LOG10) */
@@ -120,6 +127,8 @@ typedef struct {
   int64_t item_alg_bytes; /* algorithmic bytes of the item launches: each processed set's
                              rows read once (16 B per vertex + 4 B per entry), each child's
                              rows written once, 4 B per saved vertex */
+  int64_t graph_replays;  /* 1 when the call replayed a recorded HIP graph */
+  int64_t reserved[3];
 } wcc_stats;
 
 /* One record per minimum-cut evaluation (order of records is unspecified). */
@@ -204,6 +213,26 @@ int64_t wcc_threshold(int32_t criterion, int64_t n, int32_t lin_num, int32_t lin
 
 /* Human-readable text of an error code (static storage). */
 const char *wcc_strerror(int code);
+
+/* ------------------------------------------------------------------ launch shape */
+/* Launch shape of the item kernels on the current device.  It changes speed only: every
+ * shape gives the same results.  An item goes to the large bin when its scan state does
+ * not fit small_lds_kb, so small_lds_kb is the size-bin boundary. */
+typedef struct {
+  int32_t small_lds_kb; /* dynamic LDS of a small-bin workgroup, 4..64 KB (default 32) */
+  int32_t wg_per_cu;    /* small-bin workgroups per CU; 0 = as many as the LDS allows, <= 8 */
+  int32_t big_lds_kb;   /* dynamic LDS of a large-bin workgroup (one per CU), <= 159 KB */
+  int32_t big_max_pct;  /* BATCHED: most CUs (in percent) given to large-bin workgroups;
+                           0 = no large-bin launch (default 50) */
+} wcc_exec_config;
+
+/* Current shape (host out).  Environment variables WCC_LDS_KB, WCC_WG_PER_CU,
+ * WCC_BIG_LDS_KB and WCC_BIG_PCT set the initial values. */
+int wcc_get_exec_config(wcc_exec_config *cfg);
+
+/* Sets the shape used by later calls on the current device; NULL restores the
+ * defaults.  WCC_EINVAL when a field is outside its range. */
+int wcc_set_exec_config(const wcc_exec_config *cfg);
 
 /* Text describing the last failing HIP call of this thread (empty if none). */
 const char *wcc_last_error_detail(void);

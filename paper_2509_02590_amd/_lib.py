@@ -27,6 +27,7 @@ CRIT = {"log10": 0, "log2": 1, "sqrt": 2, "linear": 3}
 MODE = {"paper": 0, "kcore": 1}
 EXEC = {"plain": 0, "batched": 1}
 FLAG_VALIDATE = 1
+FLAG_NO_GRAPH = 2
 
 
 class WccError(RuntimeError):
@@ -58,7 +59,16 @@ class Stats(ctypes.Structure):
                 ("scan_steps", ctypes.c_int64), ("scan_rounds", ctypes.c_int64),
                 ("ms_front", ctypes.c_double), ("ms_items", ctypes.c_double),
                 ("ms_item_kernel", ctypes.c_double), ("item_launches", ctypes.c_int64),
-                ("ms_total", ctypes.c_double), ("item_alg_bytes", ctypes.c_int64)]
+                ("ms_total", ctypes.c_double), ("item_alg_bytes", ctypes.c_int64),
+                ("graph_replays", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ExecConfig(ctypes.Structure):
+    _fields_ = [("small_lds_kb", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("big_lds_kb", ctypes.c_int32), ("big_max_pct", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -85,6 +95,10 @@ lib.wcc_cluster_csr.argtypes = [ctypes.POINTER(Csr), _vp] + [ctypes.POINTER(ctyp
 lib.wcc_threshold.restype = ctypes.c_int64
 lib.wcc_threshold.argtypes = [_i32, _i64, _i32, _i32]
 lib.wcc_release.restype = ctypes.c_int
+lib.wcc_get_exec_config.restype = ctypes.c_int
+lib.wcc_get_exec_config.argtypes = [ctypes.POINTER(ExecConfig)]
+lib.wcc_set_exec_config.restype = ctypes.c_int
+lib.wcc_set_exec_config.argtypes = [ctypes.POINTER(ExecConfig)]
 lib.wcc_last_error_detail.restype = ctypes.c_char_p
 lib.wcc_abi_version.restype = ctypes.c_int
 
@@ -110,7 +124,7 @@ def make_csr(offsets, indices) -> Csr:
 
 
 def params(criterion="log10", s_pre=10, s_post=10, mode="kcore", exec_mode="plain", lin_num=1,
-           lin_den=1, validate=False) -> Params:
+           lin_den=1, validate=False, graph=True) -> Params:
     p = Params()
     lib.wcc_default_params(ctypes.byref(p))
     p.criterion = CRIT[criterion] if isinstance(criterion, str) else criterion
@@ -118,7 +132,7 @@ def params(criterion="log10", s_pre=10, s_post=10, mode="kcore", exec_mode="plai
     p.s_pre, p.s_post = s_pre, s_post
     p.prune_mode = MODE[mode] if isinstance(mode, str) else mode
     p.exec_mode = EXEC[exec_mode] if isinstance(exec_mode, str) else exec_mode
-    p.flags = FLAG_VALIDATE if validate else 0
+    p.flags = (FLAG_VALIDATE if validate else 0) | (0 if graph else FLAG_NO_GRAPH)
     return p
 
 
@@ -205,3 +219,22 @@ def threshold(n, criterion="log10", lin_num=1, lin_den=1) -> int:
 
 def release():
     lib.wcc_release()
+
+
+def get_exec_config() -> dict:
+    """Launch shape of the item kernels on the current device."""
+    c = ExecConfig()
+    _check(lib.wcc_get_exec_config(ctypes.byref(c)), "wcc_get_exec_config")
+    return c.as_dict()
+
+
+def set_exec_config(cfg=None, **kw):
+    """Sets the launch shape (dict or keyword fields); no argument restores the defaults."""
+    if cfg is None and not kw:
+        _check(lib.wcc_set_exec_config(None), "wcc_set_exec_config")
+        return
+    cur = get_exec_config()
+    cur.update(cfg or {})
+    cur.update(kw)
+    c = ExecConfig(**cur)
+    _check(lib.wcc_set_exec_config(ctypes.byref(c)), "wcc_set_exec_config")

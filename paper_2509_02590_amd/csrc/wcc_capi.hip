@@ -6,6 +6,7 @@
 // children there are between launches.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cstdio>
@@ -18,12 +19,17 @@
 namespace {
 
 // ---------------------------------------------------------------- workspace
+// Bumped whenever any workspace buffer moves: a recorded launch sequence (HIP graph)
+// holds raw buffer addresses and is only replayed while this value is unchanged.
+std::atomic<unsigned long long> g_alloc_gen{1};
+
 struct Buf {
   void *p = nullptr;
   size_t bytes = 0;
   int ensure(size_t b) {
     if (b <= bytes) return WCC_OK;
-    if (p) hipFree(p);
+    g_alloc_gen++;
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
     size_t nb = b + b / 8 + 256;
@@ -35,7 +41,10 @@ struct Buf {
     return WCC_OK;
   }
   void release() {
-    if (p) hipFree(p);
+    if (p) {
+      g_alloc_gen++;
+      (void)hipFree(p);
+    }
     p = nullptr;
     bytes = 0;
   }
@@ -51,16 +60,70 @@ enum BufId {
   B_VTX0, B_VTX1, B_RS0, B_RS1, B_RD0, B_RD1, B_ADJ0, B_ADJ1,
   B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SG, B_SEDGE, B_SMARK, B_GBITS,
   B_ITEMS0, B_ITEMS1, B_ITEMS_SORTED, B_SET0, B_SET_SORTED, B_IKEYS, B_IVALS, B_IKEYS2, B_IVALS2,
-  B_SPLITMEM, B_SMALL,
+  B_SPLITMEM, B_SMALL, B_LVCTL, B_LB0, B_LB1,
   B_NUM
 };
 
+// Launch shape of the item kernels: the size-bin boundary follows from the small-bin LDS
+// budget (an item goes to the large bin when its scan state does not fit it).
+struct ExecCfg : wcc_exec_config {
+  ExecCfg() {
+    small_lds_kb = 32;
+    wg_per_cu = 0;
+    big_lds_kb = 159;
+    big_max_pct = 50;
+  }
+};
+bool cfg_valid(const wcc_exec_config &c) {
+  return c.small_lds_kb >= 4 && c.small_lds_kb <= 64 && c.wg_per_cu >= 0 && c.wg_per_cu <= 8 &&
+         c.big_lds_kb >= c.small_lds_kb && c.big_lds_kb <= 159 && c.big_max_pct >= 0 && c.big_max_pct <= 100;
+}
+
+// Identity of a recorded batched run: replayed only for the same buffers and parameters.
+struct GraphKey {
+  const void *off, *idx, *mem, *out, *rec;
+  int64_t N, nnz, rec_cap;
+  int32_t obits, pad;
+  wcc_params p;
+  wcc_exec_config cfg;
+};
+
+// Sizes a batched run was planned with (host side).
+struct BatchPlan {
+  int32_t nitems = 0, nbig = 0, top_n = 0, small_max = 0;
+  size_t lds_bytes = 0, big_bytes = 0;
+  int g_big = 0, g_small = 0;
+  int64_t gbits_words = 0;
+  int64_t capS = 0, capB = 0;  // list capacities (items)
+  int levels = 0;              // levels launched (a multiple of the chunk size)
+};
+
+constexpr int LEVEL_CHUNK = 4;  // levels launched between two looks at the remaining work
+constexpr int MAX_TIMED_LEVELS = 64;
 struct Workspace {
   Buf b[B_NUM];
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evj = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evj = nullptr, evf = nullptr, evg = nullptr;
+  hipEvent_t evb0 = nullptr, evb1 = nullptr, evs0 = nullptr, evs1 = nullptr;  // per-launch timing
+  hipEvent_t lev[MAX_TIMED_LEVELS][4] = {};  // batched form: per-level launch timing
   hipStream_t s2 = nullptr;  // second stream (default priority) for the large-item launch
+  hipStream_t sg = nullptr;  // stream the recorded batched run is captured on and replayed on
   int cus = 0;
+  int dev = 0;
+  double tick_khz = 100000.0;  // device wall clock
+  ExecCfg cfg;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey;
+  GraphKey last_key;  // key of the previous eager batched call (recorded when seen twice)
+  bool last_valid = false;
+  unsigned long long ggen = 0;
+  BatchPlan gplan;
+  bool gtimed = false;  // the recorded sequence carries the per-launch timing events
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
   void release() {
+    drop_graph();
     for (auto &x : b) x.release();
   }
 };
@@ -71,6 +134,31 @@ std::mutex g_lock;
 FrontCounts *front_counts(Workspace &w) { return (FrontCounts *)(w.b[B_DCNT].as<unsigned long long>() + 128); }
 std::vector<Workspace *> g_ws;
 
+int env_int(const char *name, int dflt);
+
+int ws_init(Workspace &w, int dev, const hipDeviceProp_t &prop) {
+  w.dev = dev;
+  w.cus = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    w.tick_khz = khz;
+  HIP_TRY(hipEventCreate(&w.ev0));
+  HIP_TRY(hipEventCreate(&w.ev1));
+  HIP_TRY(hipEventCreateWithFlags(&w.evj, hipEventDisableTiming));
+  for (hipEvent_t *e : {&w.evb0, &w.evb1, &w.evs0, &w.evs1}) HIP_TRY(hipEventCreate(e));
+  for (auto &l : w.lev)
+    for (auto &e : l) HIP_TRY(hipEventCreate(&e));
+  HIP_TRY(hipEventCreateWithFlags(&w.evf, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&w.evg, hipEventDisableTiming));
+  HIP_TRY(hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&w.sg, hipStreamNonBlocking));
+  w.cfg.small_lds_kb = env_int("WCC_LDS_KB", w.cfg.small_lds_kb);
+  w.cfg.big_lds_kb = env_int("WCC_BIG_LDS_KB", w.cfg.big_lds_kb);
+  w.cfg.wg_per_cu = env_int("WCC_WG_PER_CU", w.cfg.wg_per_cu);
+  w.cfg.big_max_pct = env_int("WCC_BIG_PCT", w.cfg.big_max_pct);
+  return WCC_OK;
+}
+
 int get_ws(Workspace **out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -79,11 +167,11 @@ int get_ws(Workspace **out) {
     Workspace *w = new Workspace();
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    w->cus = prop.multiProcessorCount;
-    HIP_TRY(hipEventCreate(&w->ev0));
-    HIP_TRY(hipEventCreate(&w->ev1));
-    HIP_TRY(hipEventCreateWithFlags(&w->evj, hipEventDisableTiming));
-    HIP_TRY(hipStreamCreateWithFlags(&w->s2, hipStreamNonBlocking));
+    int rc = ws_init(*w, dev, prop);
+    if (rc) {
+      delete w;
+      return rc;
+    }
     g_ws[dev] = w;
   }
   *out = g_ws[dev];
@@ -177,10 +265,27 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
     TRY(front_validate(f, s, &ok));
     if (!ok) return WCC_EGRAPH;
   }
+  if (w.b[B_DCNT].bytes == 0) return WCC_EINVAL;
   return front_build(f, front_counts(w), w.b[B_VTX0].as<int32_t>(), w.b[B_CLSTART].as<int64_t>(),
                      want_ids ? w.b[B_CLIDS].as<int32_t>() : nullptr, w.b[B_RD0].as<int32_t>(),
                      w.b[B_RS0].as<int64_t>(), w.b[B_ADJ0].as<int32_t>(), w.b[B_ITEMS0].as<ItemDesc>(),
                      all_items ? w.b[B_SET0].as<int32_t>() : nullptr, all_items, s);
+}
+
+// CSR checks only (symmetric, simple, ids in range): WCC_EGRAPH when malformed.
+int run_validate(Workspace &w, const wcc_csr *g, hipStream_t s) {
+  TRY(w.b[B_DCNT].ensure(256 * sizeof(unsigned long long)));
+  FrontBufs f;
+  memset(&f, 0, sizeof(f));
+  f.off = g->row_offsets;
+  f.obits = g->offset_bits;
+  f.idx = g->col_indices;
+  f.N = g->num_vertices;
+  f.nnz = g->num_entries;
+  f.dcnt = w.b[B_DCNT].as<unsigned long long>();
+  int ok = 1;
+  TRY(front_validate(f, s, &ok));
+  return ok ? WCC_OK : WCC_EGRAPH;
 }
 
 int read_counts(Workspace &w, FrontCounts *h, hipStream_t s) {
@@ -209,17 +314,33 @@ int small_max_n(int64_t words, int crit, const wcc_params &p, bool split) {
 // by size (largest first) and split into two launches that run concurrently: the items
 // whose state does not fit the small LDS budget go to a workgroup per CU with the full
 // 160 KB of LDS on a second stream, the rest to many small-LDS workgroups.
+struct Shape {
+  size_t lds_bytes, big_bytes;
+  int per_cu;
+  int big_max;  // batched form: most CUs given to large-bin workgroups
+};
+int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+Shape exec_shape(const Workspace &w) {
+  Shape sh;
+  int lds_kb = clampi(w.cfg.small_lds_kb, 4, 64);
+  int big_kb = clampi(w.cfg.big_lds_kb, lds_kb, 159);
+  int fit = 160 / lds_kb;
+  int per_cu = w.cfg.wg_per_cu > 0 ? w.cfg.wg_per_cu : (fit > 8 ? 8 : fit);
+  sh.per_cu = clampi(per_cu, 1, fit < 8 ? fit : 8);
+  sh.lds_bytes = (size_t)lds_kb * 1024;
+  sh.big_bytes = (size_t)big_kb * 1024;
+  // 0 turns the large-bin launch of the batched form off (large items then run from
+  // global memory in small-bin workgroups)
+  sh.big_max = w.cfg.big_max_pct <= 0 ? 0 : clampi(w.cus * clampi(w.cfg.big_max_pct, 1, 100) / 100, 1, w.cus);
+  return sh;
+}
+
 int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, const wcc_params &p,
                int64_t *levels, double *ms_kernel, int64_t *launches, hipStream_t s) {
-  int lds_kb = env_int("WCC_LDS_KB", 32);
-  if (lds_kb < 4) lds_kb = 4;
-  if (lds_kb > 64) lds_kb = 64;
-  size_t lds_bytes = (size_t)lds_kb * 1024;
-  size_t big_bytes = (size_t)env_int("WCC_BIG_LDS_KB", 159) * 1024;
-  if (big_bytes > 159 * 1024) big_bytes = 159 * 1024;
-  int per_cu = env_int("WCC_WG_PER_CU", 0);
-  if (per_cu <= 0) per_cu = (int)(160 / lds_kb) > 8 ? 8 : (int)(160 / lds_kb);
-  if (per_cu < 1) per_cu = 1;
+  Shape shp = exec_shape(w);
+  size_t lds_bytes = shp.lds_bytes;
+  size_t big_bytes = shp.big_bytes;
+  int per_cu = shp.per_cu;
   int gmax = w.cus * per_cu;
   int32_t nitems = nitems0;
   int cur = 0;  // items in B_ITEMS0 (cur==0) or B_ITEMS1
@@ -259,15 +380,17 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     A.out_count = dcount;
     if (base.split_only) A.split_set = set_sorted;
     TRY(prim_fill32(dcount, 0u, 3, s));
-    HIP_TRY(hipEventRecord(w.ev0, s));
+    HIP_TRY(hipEventRecord(w.evf, s));
     if (nbig > 0) {
       ItemArgs Bg = A;
       Bg.items = sorted;
       Bg.nitems = nbig;
       Bg.next = dnext_big;
       Bg.lds_words = (int32_t)(big_bytes / 4);
-      HIP_TRY(hipStreamWaitEvent(w.s2, w.ev0, 0));
+      HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
+      HIP_TRY(hipEventRecord(w.evb0, w.s2));
       TRY(items_launch(Bg, grid_big, big_bytes, w.s2));
+      HIP_TRY(hipEventRecord(w.evb1, w.s2));
       HIP_TRY(hipEventRecord(w.evj, w.s2));
     }
     if (nsmall > 0) {
@@ -277,17 +400,25 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       Sm.next = dnext;
       Sm.lds_words = (int32_t)(lds_bytes / 4);
       if (base.split_only) Sm.split_set = set_sorted + nbig;
+      HIP_TRY(hipEventRecord(w.evs0, s));
       TRY(items_launch(Sm, grid_small, lds_bytes, s));
+      HIP_TRY(hipEventRecord(w.evs1, s));
     }
     if (nbig > 0) HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
-    HIP_TRY(hipEventRecord(w.ev1, s));
     int32_t nout = 0;
     HIP_TRY(hipMemcpyAsync(&nout, dcount, sizeof(nout), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     float ms = 0;
-    HIP_TRY(hipEventElapsedTime(&ms, w.ev0, w.ev1));
-    *ms_kernel += ms;
-    (*launches)++;
+    if (nbig > 0) {
+      HIP_TRY(hipEventElapsedTime(&ms, w.evb0, w.evb1));
+      *ms_kernel += ms;
+      (*launches)++;
+    }
+    if (nsmall > 0) {
+      HIP_TRY(hipEventElapsedTime(&ms, w.evs0, w.evs1));
+      *ms_kernel += ms;
+      (*launches)++;
+    }
     (*levels)++;
     if (nout > A.out_cap) return WCC_ENOMEM;
     long long errc = 0;
@@ -298,6 +429,169 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     nitems = nout;
     cur ^= 1;
   }
+  return WCC_OK;
+}
+
+// ---------------------------------------------------------------- batched form
+// Device-driven levels: every recursion depth is one launch per size bin whose item
+// count is read on the device, children go straight into the next level's small or
+// large list, and the host does not synchronise inside a run, so the whole run can be
+// recorded as one HIP graph.  Lists of parity p: small = B_ITEMS<p>, large = B_LB<p>.
+
+ItemDesc *list_small(Workspace &w, int p) { return w.b[p ? B_ITEMS1 : B_ITEMS0].as<ItemDesc>(); }
+ItemDesc *list_big(Workspace &w, int p) { return w.b[p ? B_LB1 : B_LB0].as<ItemDesc>(); }
+int32_t *level_ctl(Workspace &w) { return w.b[B_LVCTL].as<int32_t>(); }
+
+// Plans a batched run: sorts the initial items (largest first), reads back how many need
+// the large LDS budget and the largest size, and sizes grids, lists and bitmap regions.
+int plan_batched(Workspace &w, const wcc_params &p, int64_t N, int32_t nitems, BatchPlan *pl, hipStream_t s) {
+  Shape shp = exec_shape(w);
+  pl->nitems = nitems;
+  pl->lds_bytes = shp.lds_bytes;
+  pl->big_bytes = shp.big_bytes;
+  pl->small_max = small_max_n((int64_t)(shp.lds_bytes / 4), p.criterion, p, false);
+  int32_t *dnbig = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16) + 3;
+  ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
+  pl->nbig = 0;
+  pl->top_n = 0;
+  if (nitems > 0) {
+    TRY(items_sort_desc(w.b[B_ITEMS0].as<ItemDesc>(), nitems, sorted, nullptr, nullptr,
+                        w.b[B_IKEYS].as<uint32_t>(), w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(),
+                        w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p, w.b[B_TMP].bytes, s, pl->small_max, dnbig));
+    ItemDesc top;
+    HIP_TRY(hipMemcpyAsync(&top, sorted, sizeof(top), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&pl->nbig, dnbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    pl->top_n = top.n;
+  }
+  // with no large-bin launch every item stays in the small lists (large ones then run
+  // from global memory in small-bin workgroups)
+  pl->g_big = pl->nbig < shp.big_max ? pl->nbig : shp.big_max;
+  if (pl->g_big == 0) pl->nbig = 0;
+  pl->g_small = (w.cus - pl->g_big) * shp.per_cu;
+  if (pl->g_small < 1) pl->g_small = 1;
+  int cap_top = (int)wcc_k_of(p.criterion, pl->top_n > 0 ? pl->top_n : 1, p.lin_num, p.lin_den);
+  pl->gbits_words = items_bitmap_words(pl->top_n > 0 ? pl->top_n : 1, cap_top);
+  // the items of one level are disjoint vertex sets; large ones have > small_max vertices
+  pl->capS = N + 1;
+  pl->capB = N / ((int64_t)pl->small_max + 1) + 1;
+  TRY(w.b[B_LVCTL].ensure((size_t)items_level_words() * 4));
+  TRY(w.b[B_LB0].ensure((size_t)pl->capB * sizeof(ItemDesc)));
+  TRY(w.b[B_LB1].ensure((size_t)pl->capB * sizeof(ItemDesc)));
+  TRY(w.b[B_GBITS].ensure((size_t)(pl->g_big + pl->g_small) * pl->gbits_words * 8 + 64));
+  return WCC_OK;
+}
+
+// Level 0 input: the sorted initial items split into the parity-0 lists.  guard: the
+// device checks its sizes against the plan (a recorded sequence replayed on new data).
+int route_level0(Workspace &w, const ItemArgs &base, const BatchPlan &pl, bool sort, bool guard, hipStream_t s) {
+  int32_t *dnbig = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16) + 3;
+  ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
+  if (sort && pl.nitems > 0)
+    TRY(items_sort_desc(w.b[B_ITEMS0].as<ItemDesc>(), pl.nitems, sorted, nullptr, nullptr,
+                        w.b[B_IKEYS].as<uint32_t>(), w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(),
+                        w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p, w.b[B_TMP].bytes, s, pl.small_max, dnbig));
+  if (pl.g_big == 0 && pl.nitems > 0) TRY(prim_fill32(dnbig, 0u, 1, s));  // everything small
+  return items_route0(sorted, pl.nitems, dnbig, front_counts(w), guard ? pl.nitems : -1, pl.nbig, pl.top_n,
+                      list_small(w, 0), list_big(w, 0), level_ctl(w), base.cnt, s);
+}
+
+// Launches levels [L0, L1): per level, the large list on the second stream and the small
+// list on s, both writing the children into the lists of the other parity.
+int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L0, int L1, bool timed,
+                  hipStream_t s) {
+  int32_t *ctl = level_ctl(w);
+  uint64_t *gb = w.b[B_GBITS].as<uint64_t>();
+  for (int L = L0; L < L1; L++) {
+    int cur = L & 1, nx = cur ^ 1;
+    bool t = timed && L < MAX_TIMED_LEVELS;
+    TRY(items_level_prep(ctl, nx, s));
+    ItemArgs A = base;
+    A.out = list_small(w, nx);
+    A.out_count = ctl + 2 * nx;
+    A.out_cap = (int32_t)pl.capS;
+    A.out_big = pl.g_big > 0 ? list_big(w, nx) : nullptr;
+    A.out_big_count = ctl + 2 * nx + 1;
+    A.out_big_cap = (int32_t)pl.capB;
+    A.small_max = pl.small_max;
+    A.gbits_words = pl.gbits_words;
+    if (pl.g_big > 0) {
+      HIP_TRY(hipEventRecord(w.evf, s));
+      HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
+      ItemArgs Bg = A;
+      Bg.items = list_big(w, cur);
+      Bg.nitems_dev = ctl + 2 * cur + 1;
+      Bg.nitems = (int32_t)pl.capB;
+      Bg.next = ctl + items_level_words() - 1;
+      Bg.lds_words = (int32_t)(pl.big_bytes / 4);
+      Bg.gbits = gb;
+      if (t) HIP_TRY(hipEventRecord(w.lev[L][0], w.s2));
+      TRY(items_launch(Bg, pl.g_big, pl.big_bytes, w.s2));
+      if (t) HIP_TRY(hipEventRecord(w.lev[L][1], w.s2));
+      HIP_TRY(hipEventRecord(w.evj, w.s2));
+    }
+    ItemArgs Sm = A;
+    Sm.items = list_small(w, cur);
+    Sm.nitems_dev = ctl + 2 * cur;
+    Sm.nitems = (int32_t)pl.capS;
+    Sm.next = ctl + items_level_words() - 2;
+    Sm.lds_words = (int32_t)(pl.lds_bytes / 4);
+    Sm.gbits = gb + (size_t)pl.g_big * pl.gbits_words;
+    if (t) HIP_TRY(hipEventRecord(w.lev[L][2], s));
+    TRY(items_launch(Sm, pl.g_small, pl.lds_bytes, s));
+    if (t) HIP_TRY(hipEventRecord(w.lev[L][3], s));
+    if (pl.g_big > 0) HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
+  }
+  return WCC_OK;
+}
+
+// Items left in the input lists of level L (after the stream has been synchronised).
+int level_pending(Workspace &w, int L, int64_t *left, hipStream_t s) {
+  int32_t c[2];
+  HIP_TRY(hipMemcpyAsync(c, level_ctl(w) + 2 * (L & 1), sizeof(c), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *left = (int64_t)c[0] + c[1];
+  return WCC_OK;
+}
+
+// Runs levels in chunks until a level's input is empty; *L is the next level index.
+int finish_levels(Workspace &w, const ItemArgs &base, BatchPlan &pl, int *L, bool timed, hipStream_t s) {
+  for (;;) {
+    int64_t left = 0;
+    TRY(level_pending(w, *L, &left, s));
+    unsigned long long errc = 0;
+    HIP_TRY(hipMemcpyAsync(&errc, base.cnt + CNT_ERR, sizeof(errc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((long long)errc < 0) return (int)(long long)errc;
+    if (left == 0) return WCC_OK;
+    TRY(launch_levels(w, base, pl, *L, *L + LEVEL_CHUNK, timed, s));
+    *L += LEVEL_CHUNK;
+  }
+}
+
+// Summed durations and count of the item launches of levels [0, L) (after completion).
+// Timing is informative: if an event cannot be read, 0 launches are reported.
+int levels_kernel_ms(Workspace &w, const BatchPlan &pl, int L, double *ms, int64_t *launches) {
+  double tot = 0;
+  int64_t n = 0;
+  for (int l = 0; l < L && l < MAX_TIMED_LEVELS; l++) {
+    float a = 0;
+    if (pl.g_big > 0) {
+      if (hipEventElapsedTime(&a, w.lev[l][0], w.lev[l][1]) != hipSuccess) goto fail;
+      tot += a;
+      n++;
+    }
+    if (hipEventElapsedTime(&a, w.lev[l][2], w.lev[l][3]) != hipSuccess) goto fail;
+    tot += a;
+    n++;
+  }
+  *ms = tot;
+  *launches = n;
+  return WCC_OK;
+fail:
+  (void)hipGetLastError();
+  *ms = 0;
+  *launches = 0;
   return WCC_OK;
 }
 
@@ -347,8 +641,107 @@ int ensure_items(Workspace &w, int64_t cap, bool with_sets) {
   return WCC_OK;
 }
 
-int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, int32_t *out, wcc_stats *stats,
-                 wcc_record *rec, int64_t rec_cap, int64_t *nrec, hipStream_t s) {
+// Reads the device counters of a finished run into stats (and the record count).
+int collect_counts(Workspace &w, wcc_stats *st, int64_t *nrec, bool prof, hipStream_t s) {
+  unsigned long long hc[CNT_NUM];
+  FrontCounts fc;
+  unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&fc, front_counts(w), sizeof(fc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if ((long long)hc[CNT_ERR] < 0) return (int)(long long)hc[CNT_ERR];
+  st->clusters = fc.K;
+  st->intra_entries = fc.E;
+  st->items = (int64_t)hc[CNT_ITEMS];
+  st->mincuts = (int64_t)hc[CNT_MINCUTS];
+  st->accepted = (int64_t)hc[CNT_ACCEPTED];
+  st->scan_steps = (int64_t)hc[CNT_STEPS];
+  st->scan_rounds = (int64_t)hc[CNT_ROUNDS];
+  st->item_alg_bytes = (int64_t)hc[CNT_ALG_BYTES];
+  if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
+  if (prof) {
+    static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
+                                  "lists", "degree", "record", "split-rebuild", "steps", "prefetch-hits", "rounds"};
+    fprintf(stderr, "[wcc phase ms, summed over workgroups]");
+    for (int i = 0; i < 13; i++)
+      if (names[i][0])
+        fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
+    fprintf(stderr, "\n[wcc scan segments ms] pick=%.2f load+key=%.2f clear+prefetch=%.2f chunk0=%.2f more=%.2f next=%.2f\n",
+            hc[CNT_PH + 16] / 1e5, hc[CNT_PH + 17] / 1e5, hc[CNT_PH + 18] / 1e5, hc[CNT_PH + 19] / 1e5,
+            hc[CNT_PH + 20] / 1e5, hc[CNT_PH + 21] / 1e5);
+  }
+  return WCC_OK;
+}
+
+GraphKey make_key(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const wcc_params &p, int32_t *out,
+                  wcc_record *rec, int64_t rec_cap) {
+  GraphKey k;
+  memset(&k, 0, sizeof(k));
+  k.off = g->row_offsets;
+  k.idx = g->col_indices;
+  k.mem = mem_in;
+  k.out = out;
+  k.rec = rec;
+  k.N = g->num_vertices;
+  k.nnz = g->num_entries;
+  k.rec_cap = rec_cap;
+  k.obits = g->offset_bits;
+  k.p = p;
+  k.p.flags &= ~WCC_FLAG_VALIDATE;  // validation runs outside the recorded sequence
+  k.cfg = w.cfg;
+  return k;
+}
+
+// The whole batched run after validation, all on stream s with no host synchronisation:
+// front end, resets, sort, guarded routing, pl.levels levels, relabel.
+int batched_sequence(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const ItemArgs &A,
+                     const BatchPlan &pl, int32_t *out, bool timed, hipStream_t s) {
+  int64_t N = g->num_vertices;
+  TRY(run_front(w, g, mem_in, false, false, false, s));
+  TRY(prim_fill32(w.b[B_ACC].p, 0xffffffffu, N, s));
+  TRY(prim_fill32(A.cnt, 0u, 2 * CNT_NUM, s));
+  TRY(route_level0(w, A, pl, true, true, s));
+  TRY(launch_levels(w, A, pl, 0, pl.levels, timed, s));
+  TRY(items_relabel(w.b[B_ACC].as<int32_t>(), N, w.b[B_MARK].as<int32_t>(), w.b[B_RANK].as<int32_t>(), out,
+                    w.b[B_TMP].p, w.b[B_TMP].bytes, s));
+  return WCC_OK;
+}
+
+// Records batched_sequence as a HIP graph on the workspace's own stream (with the
+// per-launch timing events when the runtime records them, else without).
+int capture_batched(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const ItemArgs &A,
+                    const BatchPlan &pl, int32_t *out, const GraphKey &key) {
+  w.drop_graph();
+  unsigned long long gen0 = g_alloc_gen.load();
+  for (int timed = 1; timed >= 0; timed--) {
+    HIP_TRY(hipStreamBeginCapture(w.sg, hipStreamCaptureModeRelaxed));
+    int rc = batched_sequence(w, g, mem_in, A, pl, out, timed != 0, w.sg);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(w.sg, &graph);
+    if (rc != WCC_OK || e != hipSuccess || !graph || g_alloc_gen.load() != gen0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      if (rc != WCC_OK && rc != WCC_EHIP) return rc;
+      continue;
+    }
+    e = hipGraphInstantiate(&w.gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      w.gexec = nullptr;
+      (void)hipGetLastError();
+      continue;
+    }
+    w.gkey = key;
+    w.ggen = gen0;
+    w.gplan = pl;
+    w.gtimed = timed != 0;
+    return WCC_OK;
+  }
+  return WCC_EHIP;
+}
+
+int wcc_run_impl(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, int32_t *out,
+                 wcc_stats *stats, wcc_record *rec, int64_t rec_cap, int64_t *nrec, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   wcc_params p;
   if (pp) p = *pp;
@@ -365,53 +758,99 @@ int wcc_run_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, 
     if (stats) *stats = st;
     return WCC_OK;
   }
-  Workspace *wp;
-  TRY(get_ws(&wp));
-  Workspace &w = *wp;
+  bool validate = (p.flags & WCC_FLAG_VALIDATE) != 0;
+  bool batched = p.exec_mode == WCC_EXEC_BATCHED;
+  int prof = env_int("WCC_PROF", 0);
+  bool use_graph = batched && !(p.flags & WCC_FLAG_NO_GRAPH) && env_int("WCC_GRAPH", 1) != 0 && prof == 0;
+  GraphKey key = make_key(w, g, mem_in, p, out, rec, rec_cap);
+
+  if (use_graph && w.gexec && w.ggen == g_alloc_gen.load() && memcmp(&key, &w.gkey, sizeof(key)) == 0) {
+    // replay of the recorded batched run
+    if (validate) TRY(run_validate(w, g, s));
+    HIP_TRY(hipEventRecord(w.evf, s));
+    HIP_TRY(hipStreamWaitEvent(w.sg, w.evf, 0));
+    auto t1 = std::chrono::steady_clock::now();
+    HIP_TRY(hipGraphLaunch(w.gexec, w.sg));
+    HIP_TRY(hipEventRecord(w.evg, w.sg));
+    HIP_TRY(hipStreamWaitEvent(s, w.evg, 0));
+    BatchPlan pl = w.gplan;
+    int L = pl.levels;
+    unsigned long long errc = 0;
+    HIP_TRY(hipMemcpyAsync(&errc, w.b[B_DCNT].as<unsigned long long>() + 32 + CNT_ERR, sizeof(errc),
+                           hipMemcpyDeviceToHost, s));
+    int64_t left = 0;
+    TRY(level_pending(w, L, &left, s));
+    if ((long long)errc == WCC_ECANCELLED) {
+      // the device-side sizes differ from the recorded ones: run eagerly, record again
+      w.drop_graph();
+    } else {
+      ItemArgs A = base_args(w, p, (int32_t)(N + 1));
+      A.rec = rec;
+      A.rec_cap = rec_cap;
+      if (left > 0) {
+        // deeper recursion than recorded: finish eagerly, then relabel again
+        TRY(finish_levels(w, A, pl, &L, false, s));
+        TRY(items_relabel(w.b[B_ACC].as<int32_t>(), N, w.b[B_MARK].as<int32_t>(), w.b[B_RANK].as<int32_t>(),
+                          out, w.b[B_TMP].p, w.b[B_TMP].bytes, s));
+      }
+      TRY(collect_counts(w, &st, nrec, false, s));
+      st.ms_items = ms_since(t1);
+      st.levels = L;
+      if (w.gtimed && left == 0) TRY(levels_kernel_ms(w, pl, L, &st.ms_item_kernel, &st.item_launches));
+      st.graph_replays = 1;
+      st.ms_total = ms_since(t0);
+      if (stats) *stats = st;
+      return WCC_OK;
+    }
+  }
+
   HIP_TRY(hipEventRecord(w.ev0, s));
-  TRY(run_front(w, g, mem_in, (p.flags & WCC_FLAG_VALIDATE) != 0, false, false, s));
+  if (validate) TRY(run_validate(w, g, s));
+  TRY(run_front(w, g, mem_in, false, false, false, s));
   HIP_TRY(hipEventRecord(w.ev1, s));
-  TRY(prim_fill32(w.b[B_ACC].p, 0xffffffffu, N, s));
+  // (the counter block exists once run_front has sized the workspace)
   unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  TRY(prim_fill32(w.b[B_ACC].p, 0xffffffffu, N, s));
   TRY(prim_fill32(cnt, 0u, 2 * CNT_NUM, s));
   FrontCounts fc;
   TRY(read_counts(w, &fc, s));
   float fms = 0;
   HIP_TRY(hipEventElapsedTime(&fms, w.ev0, w.ev1));
   st.ms_front = fms;
-  st.clusters = fc.K;
-  st.intra_entries = fc.E;
   int32_t nitems = fc.nitems;
   ItemArgs A = base_args(w, p, (int32_t)(N + 1));
   A.rec = rec;
   A.rec_cap = rec_cap;
-  A.prof = env_int("WCC_PROF", 0);
+  A.prof = prof;
   auto t1 = std::chrono::steady_clock::now();
-  TRY(run_levels(w, A, nitems, p.criterion, p, &st.levels, &st.ms_item_kernel, &st.item_launches, s));
+  BatchPlan pl;
+  if (batched) {
+    TRY(plan_batched(w, p, N, nitems, &pl, s));
+    TRY(route_level0(w, A, pl, false, false, s));
+    int L = 0;
+    TRY(launch_levels(w, A, pl, 0, LEVEL_CHUNK, true, s));
+    L = LEVEL_CHUNK;
+    TRY(finish_levels(w, A, pl, &L, true, s));
+    pl.levels = L;
+    st.levels = L;
+  } else {
+    TRY(run_levels(w, A, nitems, p.criterion, p, &st.levels, &st.ms_item_kernel, &st.item_launches, s));
+  }
   TRY(items_relabel(w.b[B_ACC].as<int32_t>(), N, w.b[B_MARK].as<int32_t>(), w.b[B_RANK].as<int32_t>(), out,
                     w.b[B_TMP].p, w.b[B_TMP].bytes, s));
-  unsigned long long hc[CNT_NUM];
-  HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  TRY(collect_counts(w, &st, nrec, prof != 0, s));
+  if (batched) TRY(levels_kernel_ms(w, pl, pl.levels, &st.ms_item_kernel, &st.item_launches));
   st.ms_items = ms_since(t1);
-  st.items = (int64_t)hc[CNT_ITEMS];
-  st.mincuts = (int64_t)hc[CNT_MINCUTS];
-  st.accepted = (int64_t)hc[CNT_ACCEPTED];
-  st.scan_steps = (int64_t)hc[CNT_STEPS];
-  st.scan_rounds = (int64_t)hc[CNT_ROUNDS];
-  st.item_alg_bytes = (int64_t)hc[CNT_ALG_BYTES];
-  if (A.prof) {
-    static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
-                                  "lists", "degree", "record", "split-rebuild", "steps", "prefetch-hits", "rounds"};
-    fprintf(stderr, "[wcc phase ms, summed over workgroups]");
-    for (int i = 0; i < 13; i++)
-      if (names[i][0])
-        fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
-    fprintf(stderr, "\n[wcc scan segments ms] pick=%.2f load+key=%.2f clear+prefetch=%.2f chunk0=%.2f more=%.2f next=%.2f\n",
-            hc[CNT_PH + 16] / 1e5, hc[CNT_PH + 17] / 1e5, hc[CNT_PH + 18] / 1e5, hc[CNT_PH + 19] / 1e5,
-            hc[CNT_PH + 20] / 1e5, hc[CNT_PH + 21] / 1e5);
+  if (use_graph) {
+    // record once the same call has been seen twice; a failed recording only means later
+    // calls run eagerly too
+    if (w.last_valid && memcmp(&key, &w.last_key, sizeof(key)) == 0) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (capture_batched(w, g, mem_in, A, pl, out, key) != WCC_OK) w.drop_graph();
+    }
+    w.last_key = key;
+    w.last_valid = true;
   }
-  if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
   st.ms_total = ms_since(t0);
   if (stats) *stats = st;
   return WCC_OK;
@@ -498,7 +937,9 @@ int wcc_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p,
             wcc_stats *stats, wcc_record *records, int64_t records_cap, int64_t *num_records, void *stream) {
   std::lock_guard<std::mutex> lk(g_lock);
   try {
-    return wcc_run_impl(g, membership_in, p, membership_out, stats, records, records_cap, num_records,
+    Workspace *wp;
+    TRY(get_ws(&wp));
+    return wcc_run_impl(*wp, g, membership_in, p, membership_out, stats, records, records_cap, num_records,
                         (hipStream_t)stream);
   } catch (...) {
     return WCC_ENOMEM;
@@ -610,6 +1051,28 @@ const char *wcc_strerror(int code) {
     case WCC_EUNSUPPORTED: return "size or parameter beyond this build's limits";
   }
   return "unknown error";
+}
+
+int wcc_get_exec_config(wcc_exec_config *cfg) {
+  if (!cfg) return WCC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_lock);
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  *cfg = wp->cfg;
+  return WCC_OK;
+}
+
+int wcc_set_exec_config(const wcc_exec_config *cfg) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  ExecCfg c;
+  if (cfg) {
+    if (!cfg_valid(*cfg)) return WCC_EINVAL;
+    static_cast<wcc_exec_config &>(c) = *cfg;
+  }
+  wp->cfg = c;
+  return WCC_OK;
 }
 
 int wcc_release(void) {

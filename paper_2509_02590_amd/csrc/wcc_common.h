@@ -117,6 +117,14 @@ struct ItemArgs {
   const int32_t *split_set;         // per item: index of the caller's set
   const int32_t *split_cap;         // per set
   const int64_t *split_pos;         // per set: offset of its first vertex in the caller's order
+  // device-driven levels (batched form): the item count of the launch is read on the
+  // device, and children larger than small_max go to a second list
+  const int32_t *nitems_dev;        // when set, the launch's item count (overrides nitems),
+                                    // clamped to nitems (the list's capacity)
+  ItemDesc *out_big;                // children with n > small_max (nullptr: all go to out)
+  int32_t *out_big_count;
+  int32_t out_big_cap;
+  int32_t small_max;
 };
 
 // ---------------------------------------------------------------- device helpers

@@ -44,6 +44,11 @@ int64_t items_lds_words(int64_t n, int cap);
 int items_max_level();
 int64_t items_bitmap_words(int64_t n, int cap);
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s);
+int items_level_words();
+int items_level_prep(int32_t *ctl, int nx, hipStream_t s);
+int items_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *nbig, const FrontCounts *fc,
+                 int32_t g_nitems, int32_t g_nbig, int32_t g_top, ItemDesc *lstS, ItemDesc *lstB, int32_t *ctl,
+                 unsigned long long *cnt, hipStream_t s);
 int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t *set_in, int32_t *set_out,
                     uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
                     hipStream_t s, int small_max, int32_t *nbig);

@@ -350,8 +350,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     nx.adj[d.eb + ld(&s.C[np]) + slot] = ld(&s.E[j]) - ld(&s.D[L]);
   });
   // descriptors of the children
-  for (int i = threadIdx.x; i < n; i += IB) {
-    if (ld(&s.B[i]) != i) continue;
+  auto child = [&](int i) {
     int cs = ld(&s.D[i]);
     int sz = ld(&s.A[i]);
     int o = ld(&s.C[cs]);
@@ -363,10 +362,21 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     c.m = o1 - o;
     c.depth = d.depth + 1;
     c.flags = 0;
+    return c;
+  };
+  for (int i = threadIdx.x; i < n; i += IB) {
+    if (ld(&s.B[i]) != i) continue;
+    ItemDesc c = child(i);
     atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * c.n + 4LL * c.m));
-    int slot = atomicAdd(A.out_count, 1);
-    if (slot < A.out_cap) A.out[slot] = c;
-    else err(A, WCC_ENOMEM);
+    if (A.out_big && c.n > A.small_max) {
+      int slot = atomicAdd(A.out_big_count, 1);
+      if (slot < A.out_big_cap) A.out_big[slot] = c;
+      else err(A, WCC_ENOMEM);
+    } else {
+      int slot = atomicAdd(A.out_count, 1);
+      if (slot < A.out_cap) A.out[slot] = c;
+      else err(A, WCC_ENOMEM);
+    }
   }
   __syncthreads();
 }
@@ -898,15 +908,66 @@ __global__ void __launch_bounds__(IB) k_items(ItemArgs A) {
   extern __shared__ uint64_t dyn[];
   __shared__ Sh sh;
   __shared__ int cur;
+  // the count of a device-driven level was written by an earlier launch
+  int nit = A.nitems;
+  if (A.nitems_dev) {
+    int c = *A.nitems_dev;
+    nit = c < nit ? c : nit;
+  }
   for (;;) {
     if (threadIdx.x == 0) cur = atomicAdd(A.next, 1);
     __syncthreads();
     int it = cur;
     __syncthreads();
-    if (it >= A.nitems) break;
+    if (it >= nit) break;
     ItemDesc d = A.items[it];
     process_item(A, d, dyn, it, sh);
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- device-driven levels
+// Per-level control words: counts of the small and large lists of each parity, then the
+// work counters of the level being launched.
+enum : int32_t { LV_CS0 = 0, LV_CB0, LV_CS1, LV_CB1, LV_NEXT_S, LV_NEXT_B, LV_WORDS };
+
+// Clears the output counts of parity nx and the work counters before a level.
+__global__ void k_level_prep(int32_t *ctl, int nx) {
+  if (threadIdx.x == 0) {
+    ctl[2 * nx] = 0;
+    ctl[2 * nx + 1] = 0;
+    ctl[LV_NEXT_S] = 0;
+    ctl[LV_NEXT_B] = 0;
+  }
+}
+
+// Splits the sorted initial items into the parity-0 lists: the first *nbig (largest
+// first) are large, the rest small.  When g_nitems >= 0 the device-side sizes must equal
+// the ones the launch sequence was recorded for (item count, large count, largest n);
+// otherwise both lists stay empty and WCC_ECANCELLED is reported.
+__global__ void k_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *nbig_p, const FrontCounts *fc,
+                         int32_t g_nitems, int32_t g_nbig, int32_t g_top, ItemDesc *lstS, ItemDesc *lstB,
+                         int32_t *ctl, unsigned long long *cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t nb = nitems > 0 ? *nbig_p : 0;
+  nb = nb < 0 ? 0 : (nb > nitems ? nitems : nb);
+  bool bad = g_nitems >= 0 &&
+             (fc->nitems != g_nitems || nb != g_nbig || (nitems > 0 && sorted[0].n != g_top));
+  if (bad) {
+    if (i == 0) {
+      ctl[LV_CS0] = 0;
+      ctl[LV_CB0] = 0;
+      atomicMin((long long *)&cnt[CNT_ERR], (long long)WCC_ECANCELLED);
+    }
+    return;
+  }
+  if (i < nitems) {
+    if (i < nb) lstB[i] = sorted[i];
+    else lstS[i - nb] = sorted[i];
+  }
+  if (i == 0) {
+    ctl[LV_CB0] = nb;
+    ctl[LV_CS0] = nitems - nb;
   }
 }
 
@@ -961,13 +1022,31 @@ int64_t items_bitmap_words(int64_t n, int cap) {
 }
 
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
-  if (A.nitems <= 0) return WCC_OK;
+  if (grid <= 0 || (!A.nitems_dev && A.nitems <= 0)) return WCC_OK;
   static size_t attr_set = 0;
   if (lds_bytes > 65536 && lds_bytes > attr_set) {
     HIP_TRY(hipFuncSetAttribute((const void *)k_items, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     attr_set = lds_bytes;
   }
   hipLaunchKernelGGL(k_items, dim3(grid), dim3(IB), lds_bytes, s, A);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
+
+int items_level_words() { return LV_WORDS; }
+
+int items_level_prep(int32_t *ctl, int nx, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(64), 0, s, ctl, nx);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
+
+int items_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *nbig, const FrontCounts *fc,
+                 int32_t g_nitems, int32_t g_nbig, int32_t g_top, ItemDesc *lstS, ItemDesc *lstB, int32_t *ctl,
+                 unsigned long long *cnt, hipStream_t s) {
+  int blocks = nitems > 0 ? (nitems + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_route0, dim3(blocks), dim3(256), 0, s, sorted, nitems, nbig, fc, g_nitems, g_nbig, g_top,
+                     lstS, lstB, ctl, cnt);
   HIP_TRY(hipGetLastError());
   return WCC_OK;
 }

@@ -223,6 +223,7 @@ __global__ void k_fill32(uint32_t *p, uint32_t v, int64_t n) {
 // Fills nwords 32-bit words with v (a kernel, so that it can be captured in a graph).
 int prim_fill32(void *p, uint32_t v, int64_t nwords, hipStream_t s) {
   if (nwords <= 0) return WCC_OK;
+  if ((uintptr_t)p < 65536) return WCC_EINVAL;  // an unallocated buffer (plus an offset)
   int64_t blocks = (nwords + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)p, v, nwords);
