@@ -23,6 +23,23 @@ sys.path.insert(0, ROOT)
 METRIC = "WCC input edges processed/s (batched vs plain GPU), HBM GB/s; p50/p99 job ms"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_items launch on the default workload and form, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes scaled by a known-size copy (profiles/k_items_chunglu-1M-20M_traffic.md).
+# They describe the kernel sources with this digest only: after any change of the item
+# kernel the figure is stale and reported as null until the counters are taken again.
+TRAFFIC = {"sources_sha256_16": "771599a219a0ee9f", "workload": "chunglu-1M-20M", "exec": "batched",
+           "mode": "kcore", "bytes_per_launch": 80918016.0}
+KERNEL_SOURCES = ["paper_2509_02590_amd/csrc/wcc_items.hip", "paper_2509_02590_amd/csrc/wcc_common.h"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -61,8 +78,22 @@ def main():
     ap.add_argument("--mode", default="kcore")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-bytes", type=float, default=None,
-                    help="HBM bytes per item launch measured by rocprofv3 counters (optional)")
+                    help="HBM bytes per item launch measured by rocprofv3 counters (overrides the "
+                         "recorded figure)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 5 device-to-device copies of BYTES (the known-size kernel that "
+                         "scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d bytes 5 times" % (4 * n))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -120,6 +151,10 @@ def main():
     alg_bytes_per_launch = s0["item_alg_bytes"] / launches
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     traffic = args.traffic_bytes
+    if traffic is None and (TRAFFIC["sources_sha256_16"] == kernel_digest() and
+                            TRAFFIC["workload"] == g.meta["workload"] and TRAFFIC["exec"] == args.exec_mode
+                            and TRAFFIC["mode"] == args.mode):
+        traffic = TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "k_items",
