@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip timing the other execution form")
     ap.add_argument("--mode", default="kcore")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default launch shape instead of tuning it on this input first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-bytes", type=float, default=None,
                     help="HBM bytes per item launch measured by rocprofv3 counters (overrides the "
@@ -114,6 +116,12 @@ def main():
     mem = torch.from_numpy(g.membership).to(dev)
     out = torch.empty_like(mem)
     torch.cuda.synchronize()
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        shape, tms, ntried = wcc.autotune(off, idx, mem, reps=2, s_pre=10, s_post=10, mode=args.mode)
+        tuned = {"shape": shape, "best_ms": tms, "shapes_timed": ntried, "seconds": time.perf_counter() - t0}
+        log("autotune: %s (%.2f ms, %d shapes, %.1f s)" % (shape, tms, ntried, tuned["seconds"]))
 
     def timed(exec_mode):
         kw = dict(s_pre=10, s_post=10, mode=args.mode, exec_mode=exec_mode)
@@ -187,6 +195,9 @@ def main():
                                            "scan_rounds", "ms_front", "ms_items", "ms_item_kernel",
                                            "graph_replays")},
     }
+    line["exec_config"] = wcc.get_exec_config()
+    if tuned is not None:
+        line["autotune"] = tuned
     if other is not None:
         line["other_exec"] = other
     if not args.no_cpu_baseline:

@@ -234,6 +234,24 @@ int wcc_get_exec_config(wcc_exec_config *cfg);
  * defaults.  WCC_EINVAL when a field is outside its range. */
 int wcc_set_exec_config(const wcc_exec_config *cfg);
 
+/* Autotuner of the launch shape.  Times wcc_run (BATCHED, no graph) on the caller's
+ * input for every candidate shape -- small-bin LDS 8..64 KB (the size-bin boundary),
+ * small-bin workgroups per CU, the share of CUs for the large bin -- `reps` times each
+ * (best of reps, 1 <= reps <= 16), installs the fastest with wcc_set_exec_config and
+ * returns it.  Every shape gives the same result, so tuning never changes output.
+ *   g, membership_in, p   as for wcc_run (p may be NULL for the defaults; its
+ *                         exec_mode is ignored)
+ *   best                  host out: the chosen shape
+ *   best_ms               host out (nullable): its best wall time per run, ms
+ *   tried                 host out (nullable): number of shapes timed
+ * With the environment variable WCC_TUNE_CACHE naming a file, a shape tuned earlier
+ * for the same device, graph size and parameters is read from it instead of timed
+ * again (then *tried = 0), and a newly tuned shape is appended to it.
+ * Errors: as wcc_run; WCC_EINVAL for reps out of range or best == NULL.  The call
+ * allocates the workspace wcc_run needs and an output buffer of N int32. */
+int wcc_autotune(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, int32_t reps,
+                 wcc_exec_config *best, double *best_ms, int32_t *tried, void *stream);
+
 /* Text describing the last failing HIP call of this thread (empty if none). */
 const char *wcc_last_error_detail(void);
 

@@ -95,6 +95,9 @@ lib.wcc_cluster_csr.argtypes = [ctypes.POINTER(Csr), _vp] + [ctypes.POINTER(ctyp
 lib.wcc_threshold.restype = ctypes.c_int64
 lib.wcc_threshold.argtypes = [_i32, _i64, _i32, _i32]
 lib.wcc_release.restype = ctypes.c_int
+lib.wcc_autotune.restype = ctypes.c_int
+lib.wcc_autotune.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(ExecConfig),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), _vp]
 lib.wcc_get_exec_config.restype = ctypes.c_int
 lib.wcc_get_exec_config.argtypes = [ctypes.POINTER(ExecConfig)]
 lib.wcc_set_exec_config.restype = ctypes.c_int
@@ -238,3 +241,19 @@ def set_exec_config(cfg=None, **kw):
     cur.update(kw)
     c = ExecConfig(**cur)
     _check(lib.wcc_set_exec_config(ctypes.byref(c)), "wcc_set_exec_config")
+
+
+def autotune(offsets, indices, membership, reps=2, **kw):
+    """Times every candidate launch shape on this input (batched form), installs the
+    fastest and returns (shape dict, best ms per run, shapes timed)."""
+    import torch
+    g = make_csr(offsets, indices)
+    p = params(**kw)
+    best = ExecConfig()
+    ms = ctypes.c_double(0)
+    tried = ctypes.c_int32(0)
+    rc = lib.wcc_autotune(ctypes.byref(g), membership.data_ptr() if membership.numel() else None, ctypes.byref(p),
+                          reps, ctypes.byref(best), ctypes.byref(ms), ctypes.byref(tried),
+                          _stream(torch, membership.device))
+    _check(rc, "wcc_autotune")
+    return best.as_dict(), ms.value, tried.value

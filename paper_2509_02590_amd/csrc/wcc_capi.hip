@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "wcc_internal.h"
@@ -904,6 +905,126 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   return WCC_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+// Candidate shapes: every small-bin LDS budget (the size-bin boundary), the workgroups
+// per CU that budget allows, and the large-bin CU share.
+std::vector<ExecCfg> tune_candidates() {
+  std::vector<ExecCfg> c;
+  for (int kb : {8, 16, 24, 32, 48, 64}) {
+    int fit = 160 / kb;
+    for (int per : {0, 2, 4}) {
+      if (per > fit || (per == 0 && fit <= 4 && kb != 32)) continue;
+      for (int pct : {25, 50, 100}) {
+        ExecCfg e;
+        e.small_lds_kb = kb;
+        e.wg_per_cu = per;
+        e.big_max_pct = pct;
+        c.push_back(e);
+      }
+    }
+  }
+  return c;
+}
+
+std::string tune_key(const Workspace &w, const wcc_csr *g, const wcc_params &p) {
+  hipDeviceProp_t prop;
+  char name[300] = "gpu";
+  if (hipGetDeviceProperties(&prop, w.dev) == hipSuccess) snprintf(name, sizeof(name), "%s", prop.gcnArchName);
+  for (char *c = name; *c; c++)
+    if (*c == ' ' || *c == '|') *c = '_';
+  char k[512];
+  snprintf(k, sizeof(k), "%s|cus=%d|N=%lld|E=%lld|crit=%d/%d/%d|s=%d/%d|prune=%d", name, w.cus,
+           (long long)g->num_vertices, (long long)g->num_entries, p.criterion, p.lin_num, p.lin_den, p.s_pre,
+           p.s_post, p.prune_mode);
+  return k;
+}
+
+bool tune_cache_lookup(const char *path, const std::string &key, ExecCfg *c) {
+  FILE *f = fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char k[600];
+    int a, b, d, e;
+    if (sscanf(line, "%599s %d %d %d %d", k, &a, &b, &d, &e) == 5 && key == k) {
+      c->small_lds_kb = a;
+      c->wg_per_cu = b;
+      c->big_lds_kb = d;
+      c->big_max_pct = e;
+      found = cfg_valid(*c);  // the last valid entry for the key wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+int autotune_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp, int reps, wcc_exec_config *best,
+                  double *best_ms, int32_t *tried, hipStream_t s) {
+  wcc_params p;
+  if (pp) p = *pp;
+  else wcc_default_params(&p);
+  p.exec_mode = WCC_EXEC_BATCHED;
+  p.flags |= WCC_FLAG_NO_GRAPH;
+  p.flags &= ~WCC_FLAG_VALIDATE;
+  TRY(check_params(p));
+  TRY(check_csr(g));
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  Workspace &w = *wp;
+  if (tried) *tried = 0;
+  if (best_ms) *best_ms = 0;
+  const char *cache = getenv("WCC_TUNE_CACHE");
+  std::string key = tune_key(w, g, p);
+  ExecCfg hit;
+  if (cache && *cache && tune_cache_lookup(cache, key, &hit)) {
+    w.cfg = hit;
+    *best = hit;
+    return WCC_OK;
+  }
+  int64_t N = g->num_vertices;
+  int32_t *out = nullptr;
+  if (N > 0 && hipMalloc((void **)&out, (size_t)N * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return WCC_ENOMEM;
+  }
+  ExecCfg keep = w.cfg, win = w.cfg;
+  double win_ms = 1e300;
+  int n = 0, rc = WCC_OK;
+  for (const ExecCfg &c : tune_candidates()) {
+    w.cfg = c;
+    double t = 1e300;
+    for (int r = 0; r < reps && rc == WCC_OK; r++) {
+      wcc_stats st;
+      rc = wcc_run_impl(w, g, mem_in, &p, out, &st, nullptr, 0, nullptr, s);
+      if (rc == WCC_OK && st.ms_total < t) t = st.ms_total;
+    }
+    if (rc != WCC_OK) break;
+    n++;
+    if (t < win_ms) {
+      win_ms = t;
+      win = c;
+    }
+  }
+  if (out) (void)hipFree(out);
+  if (rc != WCC_OK) {
+    w.cfg = keep;
+    return rc;
+  }
+  w.cfg = win;
+  *best = win;
+  if (best_ms) *best_ms = win_ms;
+  if (tried) *tried = n;
+  if (cache && *cache) {
+    FILE *f = fopen(cache, "a");
+    if (f) {
+      fprintf(f, "%s %d %d %d %d\n", key.c_str(), win.small_lds_kb, win.wg_per_cu, win.big_lds_kb, win.big_max_pct);
+      fclose(f);
+    }
+  }
+  return WCC_OK;
+}
+
 }  // namespace
 
 static thread_local char g_detail[512] = "";
@@ -1051,6 +1172,17 @@ const char *wcc_strerror(int code) {
     case WCC_EUNSUPPORTED: return "size or parameter beyond this build's limits";
   }
   return "unknown error";
+}
+
+int wcc_autotune(const wcc_csr *g, const int32_t *membership_in, const wcc_params *pp, int32_t reps,
+                 wcc_exec_config *best, double *best_ms, int32_t *tried, void *stream) {
+  if (!best || reps < 1 || reps > 16) return WCC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    return autotune_impl(g, membership_in, pp, reps, best, best_ms, tried, (hipStream_t)stream);
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
 }
 
 int wcc_get_exec_config(wcc_exec_config *cfg) {

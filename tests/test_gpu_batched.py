@@ -174,3 +174,25 @@ def test_batched_c1_full_matches_plain_and_oracle():
         torch.cuda.synchronize()
         assert np.array_equal(got.cpu().numpy(), want), it
     assert st.graph_replays == 1
+
+
+def test_autotune_picks_a_shape_and_caches_it(tmp_path, monkeypatch):
+    """The autotuner times every candidate shape, installs the fastest (output stays
+    bit-exact), and a second call with a cache file reads the shape back untimed."""
+    w = _w()
+    g = gen.chung_lu(30000, 30.0, 2.5, 11, 1500, 2.0, 0.2, 0.15, 0.05, seed=8, intra_mult=1.8)
+    o, a, m = _t(g.offsets, np.int32), _t(g.indices, np.int32), _t(g.membership, np.int32)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("WCC_TUNE_CACHE", str(cache))
+    try:
+        best, ms, tried = w.autotune(o, a, m, reps=1)
+        assert tried > 20 and ms > 0
+        assert w.get_exec_config() == best
+        _compare(g.offsets, g.indices, g.membership, graph=False)
+        w.set_exec_config()
+        best2, _, tried2 = w.autotune(o, a, m, reps=1)
+        assert tried2 == 0 and best2 == best
+        with pytest.raises(w.WccError):
+            w.autotune(o, a, m, reps=0)
+    finally:
+        w.set_exec_config()
