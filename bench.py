@@ -4,7 +4,7 @@ A step is one whole wcc_run (front end, CCR, pruning, every minimum cut and spli
 final relabel) over the 1M-vertex / 20M-edge Chung-Lu workload with a planted power-law
 clustering (input already resident in HBM).  Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2|served]
                   [--exec batched|plain] [--no-compare] [--mode kcore|paper] [--no-cpu-baseline]
 
 The timed form (default batched: device-driven level launches replayed from a HIP
@@ -56,6 +56,81 @@ def workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
+def served(args, wcc, torch):
+    """Served form on a Poisson stream of whole WCC jobs (the 256-job recipe)."""
+    import numpy as np
+    import gen
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    jobs = []
+    for j in range(args.jobs):
+        g = gen.c3_job(j)
+        off = torch.from_numpy(g.offsets.astype(np.int32)).to(dev)
+        idx = torch.from_numpy(g.indices).to(dev)
+        mem = torch.from_numpy(g.membership).to(dev)
+        jobs.append(dict(off=off, idx=idx, mem=mem, out=torch.empty_like(mem), n=g.n, m=g.m))
+        if (j + 1) % 32 == 0:
+            log("generated %d jobs (%.0f s)" % (j + 1, time.perf_counter() - t0))
+    torch.cuda.synchronize()
+    tot_m = sum(j["m"] for j in jobs)
+    log("%d jobs, %.3e edges in total, generated and resident in %.0f s" % (len(jobs), tot_m, time.perf_counter() - t0))
+    kw = dict(s_pre=10, s_post=10, mode=args.mode)
+    # one at a time on the plain path: service times and the reference outputs
+    for j in jobs[:4]:
+        wcc.wcc_run(j["off"], j["idx"], j["mem"], **kw)
+    service = []
+    for j in jobs:
+        ts = time.perf_counter()
+        out, _, _ = wcc.wcc_run(j["off"], j["idx"], j["mem"], **kw)
+        torch.cuda.synchronize()
+        service.append(1000.0 * (time.perf_counter() - ts))
+        j["alone"] = out
+    service = np.array(service)
+    capacity = 1000.0 / service.mean()
+    rate = args.rate if args.rate > 0 else 2.0 * capacity
+    rng = np.random.Generator(np.random.Philox(key=3999))
+    arrivals = np.cumsum(rng.exponential(1000.0 / rate, len(jobs)))
+    arrivals -= arrivals[0]
+    # the one-at-a-time plain path under the same arrivals (FIFO, measured service times)
+    end = 0.0
+    lat_plain = []
+    for a, sv in zip(arrivals, service):
+        end = max(end, a) + sv
+        lat_plain.append(end - a)
+    plain_span = end
+    # served form
+    res = []
+    with wcc.Server(slots=args.slots) as srv:
+        h0 = time.perf_counter()
+        for i, (a, j) in enumerate(zip(arrivals, jobs)):
+            while 1000.0 * (time.perf_counter() - h0) < a:
+                res += srv.poll()
+                time.sleep(0.0002)
+            srv.submit(j["off"], j["idx"], j["mem"], j["out"], tag=i, **kw)
+        srv.wait()
+        res += srv.poll()
+    bad = [r for r in res if r["status"] != 0]
+    if bad:
+        raise SystemExit("served jobs failed: %s" % bad[:3])
+    lat = np.array([r["t_end_ms"] - r["t_submit_ms"] for r in res])
+    span = max(r["t_end_ms"] for r in res) - min(r["t_submit_ms"] for r in res)
+    equal = all(bool(torch.equal(jobs[r["tag"]]["out"], jobs[r["tag"]]["alone"])) for r in res)
+    line = {
+        "metric": METRIC, "value": tot_m / (span / 1000.0), "unit": "edges/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": span, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "served-%d-jobs" % len(jobs), "jobs": len(jobs), "edges": tot_m,
+                   "slots": args.slots, "rate_jobs_per_s": rate, "plain_capacity_jobs_per_s": capacity,
+                   "prune": args.mode, "criterion": "log10", "s_pre": 10, "s_post": 10},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "equal_output_alone_and_mixed": equal,
+        "plain_one_at_a_time": {"value": tot_m / (plain_span / 1000.0), "p50_ms": float(np.percentile(lat_plain, 50)),
+                                "p99_ms": float(np.percentile(lat_plain, 99)),
+                                "service_ms_mean": float(service.mean())},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(g, mode, threads):
     """The oracle, as it stands, on the same workload (one full run)."""
     import oracle
@@ -76,6 +151,10 @@ def main():
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip timing the other execution form")
     ap.add_argument("--mode", default="kcore")
+    ap.add_argument("--jobs", type=int, default=256, help="served: jobs in the stream")
+    ap.add_argument("--slots", type=int, default=4, help="served: concurrent jobs")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="served: arrivals per second (default: twice the plain path's capacity)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default launch shape instead of tuning it on this input first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -100,6 +179,11 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "served":
+        import torch
+        import paper_2509_02590_amd as wcc
+        served(args, wcc, torch)
+        return
 
     import numpy as np
     import torch

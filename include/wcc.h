@@ -252,6 +252,58 @@ int wcc_set_exec_config(const wcc_exec_config *cfg);
 int wcc_autotune(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, int32_t reps,
                  wcc_exec_config *best, double *best_ms, int32_t *tried, void *stream);
 
+/* ------------------------------------------------------------------ served form */
+/* A request loop for whole WCC jobs on the current device.  `slots` worker threads each
+ * own a workspace and streams, so admitted jobs run concurrently and their kernels
+ * overlap on the device.  Jobs are admitted first-in first-out when a slot is free and
+ * the job's estimated workspace fits the HBM budget (idle slots give back their cached
+ * workspace when that makes room); a slot takes the next job as soon as its job ends. */
+typedef struct {
+  int32_t slots;      /* concurrent jobs, 1..16 */
+  int32_t reserved;
+  int64_t pool_bytes; /* HBM budget for the slots' workspaces; 0 = 80% of free memory */
+} wcc_server_cfg;
+
+typedef struct wcc_server wcc_server;
+
+typedef struct {
+  wcc_csr g;                     /* device CSR; caller-owned, valid until the job's result is polled */
+  const int32_t *membership_in;  /* device, N */
+  int32_t *membership_out;       /* device, N, caller-allocated */
+  wcc_params params;             /* as for wcc_run (no graph recording in the served form) */
+  int64_t tag;                   /* caller's value, echoed in the result */
+} wcc_job;
+
+typedef struct {
+  int64_t job_id;                /* from wcc_server_submit */
+  int64_t tag;
+  int32_t status;                /* WCC_OK or a negative error code (WCC_ENOMEM: larger than the budget) */
+  int32_t slot;                  /* worker that ran it, -1 if never started */
+  double t_submit_ms;            /* server clock: milliseconds since wcc_server_create */
+  double t_start_ms;             /* admitted on a slot */
+  double t_end_ms;               /* membership_out complete on the device */
+  int64_t footprint_bytes;       /* workspace estimate used for admission */
+  wcc_stats stats;
+} wcc_result;
+
+/* Starts the worker threads (host out *out).  WCC_EINVAL for slots outside 1..16. */
+int wcc_server_create(const wcc_server_cfg *cfg, wcc_server **out);
+
+/* Queues a job (non-blocking; the job struct is copied).  *job_id (host out) numbers jobs
+ * from 1.  WCC_EINVAL for malformed arguments, WCC_ECANCELLED after destroy began. */
+int wcc_server_submit(wcc_server *srv, const wcc_job *job, int64_t *job_id);
+
+/* Moves up to max completed results into out (host array); *n (host out) = how many. */
+int wcc_server_poll(wcc_server *srv, wcc_result *out, int32_t max, int32_t *n);
+
+/* Blocks until every submitted job has completed (WCC_ETIMEOUT after timeout_ms if
+ * timeout_ms >= 0). */
+int wcc_server_wait(wcc_server *srv, int64_t timeout_ms);
+
+/* Lets running jobs finish, drops queued ones, joins the workers and frees every slot's
+ * workspace.  Results not yet polled are discarded. */
+int wcc_server_destroy(wcc_server *srv);
+
 /* Text describing the last failing HIP call of this thread (empty if none). */
 const char *wcc_last_error_detail(void);
 

@@ -7,7 +7,7 @@ Importing it fails loudly when the library has not been built.
 from ._lib import (CRIT, EXEC, MODE, RECORD_DTYPE, ExecConfig, Params, Stats, WccError, autotune,  # noqa: F401
                    cluster_csr,
                    get_exec_config, lib, make_csr, mincut_split, mincut_split_batch, params, release,
-                   set_exec_config, threshold, wcc_run)
+                   Server, set_exec_config, threshold, wcc_run)
 
 __all__ = ["wcc_run", "mincut_split", "mincut_split_batch", "cluster_csr", "threshold", "params",
-           "WccError", "RECORD_DTYPE", "release", "get_exec_config", "set_exec_config", "autotune"]
+           "WccError", "RECORD_DTYPE", "release", "get_exec_config", "set_exec_config", "autotune", "Server"]

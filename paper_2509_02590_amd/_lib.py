@@ -95,6 +95,31 @@ lib.wcc_cluster_csr.argtypes = [ctypes.POINTER(Csr), _vp] + [ctypes.POINTER(ctyp
 lib.wcc_threshold.restype = ctypes.c_int64
 lib.wcc_threshold.argtypes = [_i32, _i64, _i32, _i32]
 lib.wcc_release.restype = ctypes.c_int
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pool_bytes", ctypes.c_int64)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("g", Csr), ("membership_in", _vp), ("membership_out", _vp), ("params", Params),
+                ("tag", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("job_id", ctypes.c_int64), ("tag", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("slot", ctypes.c_int32), ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double),
+                ("t_end_ms", ctypes.c_double), ("footprint_bytes", ctypes.c_int64), ("stats", Stats)]
+
+
+lib.wcc_server_create.restype = ctypes.c_int
+lib.wcc_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(_vp)]
+lib.wcc_server_submit.restype = ctypes.c_int
+lib.wcc_server_submit.argtypes = [_vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_int64)]
+lib.wcc_server_poll.restype = ctypes.c_int
+lib.wcc_server_poll.argtypes = [_vp, ctypes.POINTER(Result), _i32, ctypes.POINTER(ctypes.c_int32)]
+lib.wcc_server_wait.restype = ctypes.c_int
+lib.wcc_server_wait.argtypes = [_vp, _i64]
+lib.wcc_server_destroy.restype = ctypes.c_int
+lib.wcc_server_destroy.argtypes = [_vp]
 lib.wcc_autotune.restype = ctypes.c_int
 lib.wcc_autotune.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(ExecConfig),
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), _vp]
@@ -257,3 +282,56 @@ def autotune(offsets, indices, membership, reps=2, **kw):
                           _stream(torch, membership.device))
     _check(rc, "wcc_autotune")
     return best.as_dict(), ms.value, tried.value
+
+
+class Server:
+    """The served form: a request loop with `slots` concurrent jobs admitted by HBM
+    footprint.  Device tensors of a submitted job are kept referenced until its result
+    has been polled."""
+
+    def __init__(self, slots=4, pool_bytes=0):
+        cfg = ServerCfg(slots, 0, pool_bytes)
+        h = _vp()
+        _check(lib.wcc_server_create(ctypes.byref(cfg), ctypes.byref(h)), "wcc_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, offsets, indices, membership, out, tag=0, **kw):
+        g = make_csr(offsets, indices)
+        j = Job(g, membership.data_ptr() if membership.numel() else None,
+                out.data_ptr() if out.numel() else None, params(**kw), tag)
+        jid = ctypes.c_int64(0)
+        _check(lib.wcc_server_submit(self._h, ctypes.byref(j), ctypes.byref(jid)), "wcc_server_submit")
+        self._keep[jid.value] = (offsets, indices, membership, out)
+        return jid.value
+
+    def poll(self, max_results=256):
+        buf = (Result * max_results)()
+        n = ctypes.c_int32(0)
+        _check(lib.wcc_server_poll(self._h, buf, max_results, ctypes.byref(n)), "wcc_server_poll")
+        res = []
+        for r in buf[:n.value]:
+            self._keep.pop(r.job_id, None)
+            res.append({"job_id": r.job_id, "tag": r.tag, "status": r.status, "slot": r.slot,
+                        "t_submit_ms": r.t_submit_ms, "t_start_ms": r.t_start_ms, "t_end_ms": r.t_end_ms,
+                        "footprint_bytes": r.footprint_bytes, "stats": r.stats.as_dict()})
+        return res
+
+    def wait(self, timeout_ms=-1):
+        rc = lib.wcc_server_wait(self._h, timeout_ms)
+        if rc == -7:
+            return False
+        _check(rc, "wcc_server_wait")
+        return True
+
+    def close(self):
+        if self._h:
+            _check(lib.wcc_server_destroy(self._h), "wcc_server_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

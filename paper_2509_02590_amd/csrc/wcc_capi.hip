@@ -11,7 +11,10 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -126,6 +129,22 @@ struct Workspace {
   void release() {
     drop_graph();
     for (auto &x : b) x.release();
+  }
+  int64_t bytes() const {
+    int64_t t = 0;
+    for (auto &x : b) t += (int64_t)x.bytes;
+    return t;
+  }
+  // streams and events (the served form creates and destroys whole workspaces)
+  void destroy() {
+    release();
+    for (hipEvent_t e : {ev0, ev1, evj, evf, evg, evb0, evb1, evs0, evs1})
+      if (e) (void)hipEventDestroy(e);
+    for (auto &l : lev)
+      for (auto &e : l)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t st : {s2, sg})
+      if (st) (void)hipStreamDestroy(st);
   }
 };
 
@@ -1025,7 +1044,139 @@ int autotune_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp,
   return WCC_OK;
 }
 
+// Workspace a job of N vertices and nnz entries grows to (the sizes run_front and the
+// level driver ensure, with Buf's slack), for admission by HBM footprint.
+int64_t est_workspace_bytes(int64_t N, int64_t nnz) {
+  int64_t n1 = N + 1;
+  int64_t b = 24 * 4 * N      // per-vertex int32 buffers of the front end and scratch
+              + 3 * 8 * N     // rs0, rs1, cluster starts
+              + 4 * N         // cluster ids
+              + 3 * 32 * n1   // item lists and the sorted list
+              + 4 * 4 * n1    // item sort keys / values
+              + 3 * 4 * nnz   // two adjacency arenas and the crossing lists
+              + nnz           // contraction marks
+              + 2 * 8 * N     // radix / scan temporaries (upper bound)
+              + (4 << 20);    // counters, large lists, bitmap regions (small)
+  return b + b / 8 + 64 * 1024;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------- served form
+struct wcc_server {
+  struct Job {
+    wcc_job j;
+    int64_t id;
+    double t_submit;
+    int64_t est;
+  };
+  int dev = 0;
+  int slots = 1;
+  int64_t budget = 0;
+  std::mutex mu;
+  std::condition_variable cv;       // work arrived / budget freed / stop
+  std::condition_variable cv_done;  // a job completed
+  std::deque<Job> pending;
+  std::vector<wcc_result> done;
+  std::vector<Workspace *> ws;
+  std::vector<hipStream_t> st;
+  std::vector<int64_t> retained;    // workspace bytes a slot holds
+  std::vector<char> busy;
+  std::vector<std::thread> th;
+  bool stop = false;
+  int64_t next_id = 1;
+  int64_t inflight = 0;             // submitted and not completed
+  std::chrono::steady_clock::time_point t0;
+
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  int64_t total_retained() const {
+    int64_t t = 0;
+    for (int64_t r : retained) t += r;
+    return t;
+  }
+  // Called with mu held: can slot i start the head job?  May release idle slots'
+  // cached workspaces to make room.  Sets *fail when the job can never fit.
+  bool admissible(int i, bool *fail) {
+    *fail = false;
+    const Job &jb = pending.front();
+    int64_t need = jb.est > retained[i] ? jb.est - retained[i] : 0;
+    if (total_retained() + need <= budget) return true;
+    for (int k = 0; k < slots; k++)
+      if (k != i && !busy[k] && retained[k] > 0) {
+        ws[k]->release();
+        retained[k] = 0;
+        if (total_retained() + need <= budget) return true;
+      }
+    bool any_busy = false;
+    for (int k = 0; k < slots; k++) any_busy = any_busy || busy[k];
+    if (!any_busy) {
+      // nothing else holds memory: release this slot's cache too, then it fits or never will
+      ws[i]->release();
+      retained[i] = 0;
+      if (jb.est <= budget) return true;
+      *fail = true;
+    }
+    return false;
+  }
+  void worker(int i) {
+    (void)hipSetDevice(dev);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      bool fail = false;
+      cv.wait(lk, [&] { return stop || (!pending.empty() && (admissible(i, &fail) || fail)); });
+      if (stop) break;
+      Job jb = pending.front();
+      pending.pop_front();
+      if (fail) {
+        wcc_result r;
+        memset(&r, 0, sizeof(r));
+        r.job_id = jb.id;
+        r.tag = jb.j.tag;
+        r.status = WCC_ENOMEM;
+        r.slot = -1;
+        r.t_submit_ms = jb.t_submit;
+        r.t_start_ms = r.t_end_ms = now_ms();
+        r.footprint_bytes = jb.est;
+        done.push_back(r);
+        inflight--;
+        cv_done.notify_all();
+        cv.notify_all();
+        continue;
+      }
+      busy[i] = 1;
+      if (jb.est > retained[i]) retained[i] = jb.est;  // reserved while it runs
+      cv.notify_all();  // the next job may fit on another slot
+      lk.unlock();
+      wcc_result r;
+      memset(&r, 0, sizeof(r));
+      r.job_id = jb.id;
+      r.tag = jb.j.tag;
+      r.slot = i;
+      r.t_submit_ms = jb.t_submit;
+      r.footprint_bytes = jb.est;
+      r.t_start_ms = now_ms();
+      wcc_params p = jb.j.params;
+      p.flags |= WCC_FLAG_NO_GRAPH;
+      int rc = wcc_run_impl(*ws[i], &jb.j.g, jb.j.membership_in, &p, jb.j.membership_out, &r.stats, nullptr, 0,
+                            nullptr, st[i]);
+      if (rc == WCC_OK && hipStreamSynchronize(st[i]) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = WCC_EHIP;
+      }
+      r.status = rc;
+      r.t_end_ms = now_ms();
+      lk.lock();
+      busy[i] = 0;
+      retained[i] = ws[i]->bytes();
+      done.push_back(r);
+      inflight--;
+      cv_done.notify_all();
+      cv.notify_all();
+    }
+  }
+};
 
 static thread_local char g_detail[512] = "";
 
@@ -1183,6 +1334,113 @@ int wcc_autotune(const wcc_csr *g, const int32_t *membership_in, const wcc_param
   } catch (...) {
     return WCC_ENOMEM;
   }
+}
+
+int wcc_server_create(const wcc_server_cfg *cfg, wcc_server **out) {
+  if (!cfg || !out || cfg->slots < 1 || cfg->slots > 16 || cfg->pool_bytes < 0) return WCC_EINVAL;
+  *out = nullptr;
+  try {
+    wcc_server *sv = new wcc_server();
+    int rc = WCC_OK;
+    HIP_TRY(hipGetDevice(&sv->dev));
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    sv->budget = cfg->pool_bytes > 0 ? cfg->pool_bytes : (int64_t)(fr / 10 * 8);
+    sv->slots = cfg->slots;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, sv->dev));
+    for (int i = 0; i < sv->slots && rc == WCC_OK; i++) {
+      Workspace *w = new Workspace();
+      rc = ws_init(*w, sv->dev, prop);
+      hipStream_t s1 = nullptr;
+      if (rc == WCC_OK && hipStreamCreateWithFlags(&s1, hipStreamNonBlocking) != hipSuccess) rc = WCC_EHIP;
+      sv->ws.push_back(w);
+      sv->st.push_back(s1);
+      sv->retained.push_back(0);
+      sv->busy.push_back(0);
+    }
+    if (rc != WCC_OK) {
+      for (size_t i = 0; i < sv->ws.size(); i++) {
+        sv->ws[i]->destroy();
+        delete sv->ws[i];
+        if (sv->st[i]) (void)hipStreamDestroy(sv->st[i]);
+      }
+      delete sv;
+      return rc;
+    }
+    sv->t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < sv->slots; i++) sv->th.emplace_back([sv, i] { sv->worker(i); });
+    *out = sv;
+    return WCC_OK;
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int wcc_server_submit(wcc_server *sv, const wcc_job *job, int64_t *job_id) {
+  if (!sv || !job) return WCC_EINVAL;
+  int rc = check_params(job->params);
+  if (rc == WCC_OK) rc = check_csr(&job->g);
+  if (rc != WCC_OK) return rc;
+  if (job->g.num_vertices > 0 && (!job->membership_in || !job->membership_out)) return WCC_EINVAL;
+  try {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return WCC_ECANCELLED;
+    wcc_server::Job jb;
+    jb.j = *job;
+    jb.id = sv->next_id++;
+    jb.t_submit = sv->now_ms();
+    jb.est = est_workspace_bytes(job->g.num_vertices, job->g.num_entries);
+    sv->pending.push_back(jb);
+    sv->inflight++;
+    if (job_id) *job_id = jb.id;
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+  sv->cv.notify_all();
+  return WCC_OK;
+}
+
+int wcc_server_poll(wcc_server *sv, wcc_result *out, int32_t max, int32_t *n) {
+  if (!sv || !n || max < 0 || (max > 0 && !out)) return WCC_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  int32_t k = 0;
+  while (k < max && !sv->done.empty()) {
+    out[k++] = sv->done.front();
+    sv->done.erase(sv->done.begin());
+  }
+  *n = k;
+  return WCC_OK;
+}
+
+int wcc_server_wait(wcc_server *sv, int64_t timeout_ms) {
+  if (!sv) return WCC_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto idle = [&] { return sv->inflight == 0; };
+  if (timeout_ms < 0) {
+    sv->cv_done.wait(lk, idle);
+    return WCC_OK;
+  }
+  return sv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), idle) ? WCC_OK : WCC_ETIMEOUT;
+}
+
+int wcc_server_destroy(wcc_server *sv) {
+  if (!sv) return WCC_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+    sv->inflight -= (int64_t)sv->pending.size();
+    sv->pending.clear();
+  }
+  sv->cv.notify_all();
+  for (auto &t : sv->th) t.join();
+  for (size_t i = 0; i < sv->ws.size(); i++) {
+    sv->ws[i]->destroy();
+    delete sv->ws[i];
+    if (sv->st[i]) (void)hipStreamDestroy(sv->st[i]);
+  }
+  delete sv;
+  return WCC_OK;
 }
 
 int wcc_get_exec_config(wcc_exec_config *cfg) {

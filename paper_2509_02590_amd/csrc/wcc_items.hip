@@ -28,6 +28,8 @@
 // Passes over all edges of an item are entry-parallel: each thread takes 16 consecutive
 // entries (coalesced loads) and finds their owners by a binary search in the LDS copy
 // of the row starts.
+#include <mutex>
+
 #include "wcc_internal.h"
 
 namespace {
@@ -1023,10 +1025,17 @@ int64_t items_bitmap_words(int64_t n, int cap) {
 
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
   if (grid <= 0 || (!A.nitems_dev && A.nitems <= 0)) return WCC_OK;
-  static size_t attr_set = 0;
-  if (lds_bytes > 65536 && lds_bytes > attr_set) {
-    HIP_TRY(hipFuncSetAttribute((const void *)k_items, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-    attr_set = lds_bytes;
+  if (lds_bytes > 65536) {
+    // raised once per process to the largest budget any launch uses (threads of the
+    // served form launch concurrently)
+    static std::once_flag once;
+    static hipError_t attr_rc = hipSuccess;
+    std::call_once(once, [] {
+      attr_rc = hipFuncSetAttribute((const void *)k_items, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(159 * 1024));
+    });
+    HIP_TRY(attr_rc);
+    if (lds_bytes > 159 * 1024) return WCC_EINVAL;
   }
   hipLaunchKernelGGL(k_items, dim3(grid), dim3(IB), lds_bytes, s, A);
   HIP_TRY(hipGetLastError());
