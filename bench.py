@@ -75,6 +75,7 @@ def served(args, wcc, torch):
     tot_m = sum(j["m"] for j in jobs)
     log("%d jobs, %.3e edges in total, generated and resident in %.0f s" % (len(jobs), tot_m, time.perf_counter() - t0))
     kw = dict(s_pre=10, s_post=10, mode=args.mode)
+    skw = dict(kw, exec_mode=args.served_exec)
     # one at a time on the plain path: service times and the reference outputs
     for j in jobs[:4]:
         wcc.wcc_run(j["off"], j["idx"], j["mem"], **kw)
@@ -106,7 +107,7 @@ def served(args, wcc, torch):
             while 1000.0 * (time.perf_counter() - h0) < a:
                 res += srv.poll()
                 time.sleep(0.0002)
-            srv.submit(j["off"], j["idx"], j["mem"], j["out"], tag=i, **kw)
+            srv.submit(j["off"], j["idx"], j["mem"], j["out"], tag=i, **skw)
         srv.wait()
         res += srv.poll()
     bad = [r for r in res if r["status"] != 0]
@@ -120,7 +121,8 @@ def served(args, wcc, torch):
         "steps": 1, "warmup": 0, "ms_per_step": span, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "served-%d-jobs" % len(jobs), "jobs": len(jobs), "edges": tot_m,
-                   "slots": args.slots, "rate_jobs_per_s": rate, "plain_capacity_jobs_per_s": capacity,
+                   "slots": args.slots, "served_exec": args.served_exec,
+                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"), "rate_jobs_per_s": rate, "plain_capacity_jobs_per_s": capacity,
                    "prune": args.mode, "criterion": "log10", "s_pre": 10, "s_post": 10},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "equal_output_alone_and_mixed": equal,
@@ -152,7 +154,8 @@ def main():
                     help="skip timing the other execution form")
     ap.add_argument("--mode", default="kcore")
     ap.add_argument("--jobs", type=int, default=256, help="served: jobs in the stream")
-    ap.add_argument("--slots", type=int, default=4, help="served: concurrent jobs")
+    ap.add_argument("--slots", type=int, default=8, help="served: concurrent jobs")
+    ap.add_argument("--served-exec", default="plain", help="served: execution form of each job")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="served: arrivals per second (default: twice the plain path's capacity)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
@@ -180,6 +183,8 @@ def main():
               "(sharding across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "served":
+        # concurrent jobs need hardware queues of their own (HIP's default is 4)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
         import torch
         import paper_2509_02590_amd as wcc
         served(args, wcc, torch)

@@ -149,7 +149,9 @@ def c1(seed: int = 1001, n: int = 1_000_000) -> Graph:
 
 
 def c2(seed: int = 1002, n: int = 10_000_000) -> Graph:
-    g = chung_lu(n, 40.0, 2.3, 11, 100_000, 1.8, 0.25, 0.20, 0.0, 3, seed=seed)
+    # intra_mult offsets duplicate intra-cluster pairs so that m ~ 2.0e8 and the
+    # mixing ~ 0.25 are reached (measured: m = 201,915,650, mixing 0.247)
+    g = chung_lu(n, 40.0, 2.3, 11, 100_000, 1.8, 0.25, 0.20, 0.0, 3, seed=seed, intra_mult=1.4)
     g.meta["workload"] = "chunglu-10M-200M"
     return g
 

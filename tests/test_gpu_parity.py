@@ -202,3 +202,20 @@ def test_wcc_c1_full_kcore():
     g = gen.c1()
     st = _compare(g.offsets, g.indices, g.membership, mode="kcore")
     assert st.mincuts > 1000
+
+
+@pytest.mark.parametrize("exec_mode", ["plain", "batched"])
+def test_wcc_global_state_items(exec_mode):
+    """Items whose scan state does not fit the large bin's LDS run from global memory:
+    forced here by tiny LDS budgets, checked against the oracle."""
+    w = _w()
+    g = gen.chung_lu(60000, 30.0, 2.5, 11, 2000, 2.0, 0.2, 0.15, 0.05, seed=77, intra_mult=1.8)
+    try:
+        w.set_exec_config(small_lds_kb=4, big_lds_kb=4, big_max_pct=50)
+        for mode in ("kcore", "paper"):
+            want, wrec = oracle.wcc(g.offsets, g.indices, g.membership, mode=mode)
+            got, st, grec = _run(g.offsets, g.indices, g.membership, mode=mode, exec_mode=exec_mode, graph=False)
+            assert np.array_equal(got, want), mode
+            assert _rec_key(grec) == _rec_key(wrec)
+    finally:
+        w.set_exec_config()
