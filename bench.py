@@ -53,6 +53,8 @@ def workload(name):
         return gen.c1()
     if name == "c2":
         return gen.c2()
+    if name == "c4":
+        return gen.c4()
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -133,6 +135,51 @@ def served(args, wcc, torch):
     print(json.dumps(line), flush=True)
 
 
+def cm_sets(comp, torch):
+    """Sets of the CM-style call from CCR labels: components larger than s_pre = 10, their
+    vertices ascending, grouped by label; caps k(n) under log10."""
+    n = comp.numel()
+    lab = torch.where(comp >= 0, comp, torch.full_like(comp, n)).long()
+    size = torch.bincount(lab, minlength=n + 1)[:n]
+    keep = (comp >= 0) & (size[lab.clamp(max=n - 1)] > 10)
+    vid = torch.nonzero(keep).flatten()
+    order = torch.argsort(lab[vid], stable=True)
+    verts = vid[order].to(torch.int32).contiguous()
+    ksz = size[size > 10]
+    set_off = torch.zeros(ksz.numel() + 1, dtype=torch.int64, device=comp.device)
+    set_off[1:] = torch.cumsum(ksz, 0)
+    caps = torch.ones_like(ksz, dtype=torch.int32)
+    p = 10
+    while True:
+        big = ksz >= p
+        if not bool(big.any()):
+            break
+        caps += big.to(torch.int32)
+        p *= 10
+    return verts, set_off, caps
+
+
+def cm_split(g, off, idx, mem, wcc, torch, reps):
+    """The CM-style call: CCR components (larger than s_pre = 10) of every cluster, then one
+    mincut_split_batch over all of them with cap = k(n) (log10)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    comp = wcc.ccr_components(off, idx, mem)
+    torch.cuda.synchronize()
+    t_ccr = time.perf_counter() - t0
+    verts, set_off, caps = cm_sets(comp, torch)
+    best = 1e30
+    for _ in range(max(1, reps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, side = wcc.mincut_split_batch(off, idx, verts, set_off, caps)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    below = int((lam < caps).sum().item())
+    return {"sets": int(caps.numel()), "vertices": int(verts.numel()), "ms_ccr": 1000.0 * t_ccr,
+            "ms_split_batch": 1000.0 * best, "edges_per_s": g.m / best, "below_cap": below}
+
+
 def cpu_baseline(g, mode, threads):
     """The oracle, as it stands, on the same workload (one full run)."""
     import oracle
@@ -161,6 +208,8 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default launch shape instead of tuning it on this input first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cm", action="store_true",
+                    help="also time the CM-style mincut_split_batch over every CCR component")
     ap.add_argument("--traffic-bytes", type=float, default=None,
                     help="HBM bytes per item launch measured by rocprofv3 counters (overrides the "
                          "recorded figure)")
@@ -284,6 +333,9 @@ def main():
                                            "scan_rounds", "ms_front", "ms_items", "ms_item_kernel",
                                            "graph_replays")},
     }
+    if args.cm:
+        line["cm_split_batch"] = cm_split(g, off, idx, mem, wcc, torch, reps=max(1, min(args.steps, 3)))
+        log("cm split batch: %s" % line["cm_split_batch"])
     line["exec_config"] = wcc.get_exec_config()
     if tuned is not None:
         line["autotune"] = tuned

@@ -170,6 +170,8 @@ def c3_job(j: int, seed_base: int = 3000) -> Graph:
 
 
 def c4(seed: int = 1004, n: int = 250_000_000) -> Graph:
-    g = chung_lu(n, 16.0, 2.2, 11, 1_000_000, 1.9, 0.3, 0.07, 0.03, 1, wmax=1e6, seed=seed)
+    # intra_mult offsets duplicate intra-cluster pairs (at a tenth of the size it gives
+    # m ~ 2.0e8 and mixing ~ 0.29; the full size is reported by the run that uses it)
+    g = chung_lu(n, 16.0, 2.2, 11, 1_000_000, 1.9, 0.3, 0.07, 0.03, 1, wmax=1e6, seed=seed, intra_mult=1.5)
     g.meta["workload"] = "chunglu-250M-2B"
     return g

@@ -22,6 +22,7 @@
  */
 #include <math.h>
 #include <pthread.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -117,19 +118,38 @@ typedef struct {
   void *ctx;
   int64_t ntasks;
   int64_t next;
+  int64_t done;
+  const char *name;
 } pool_job;
+
+/* With WCCGEN_VERBOSE set, every phase reports each eighth of its tasks on stderr (long
+ * generations otherwise print nothing for minutes). */
+static int gen_verbose(void) {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("WCCGEN_VERBOSE");
+    v = e && *e && *e != '0';
+  }
+  return v;
+}
 
 static void *pool_worker(void *arg) {
   pool_job *j = (pool_job *)arg;
+  int64_t step = (j->ntasks + 7) / 8;
   for (;;) {
     int64_t t = __atomic_fetch_add(&j->next, 1, __ATOMIC_RELAXED);
     if (t >= j->ntasks) break;
     j->fn(j->ctx, t);
+    int64_t d = __atomic_add_fetch(&j->done, 1, __ATOMIC_RELAXED);
+    if (gen_verbose() && step > 0 && (d % step == 0 || d == j->ntasks)) {
+      fprintf(stderr, "[gen] %s %lld/%lld tasks\n", j->name, (long long)d, (long long)j->ntasks);
+      fflush(stderr);
+    }
   }
   return NULL;
 }
-static void parallel_for(int nthreads, int64_t ntasks, task_fn fn, void *ctx) {
-  pool_job j = {fn, ctx, ntasks, 0};
+static void parallel_for_named(const char *name, int nthreads, int64_t ntasks, task_fn fn, void *ctx) {
+  pool_job j = {fn, ctx, ntasks, 0, 0, name};
   if (nthreads <= 1 || ntasks <= 1) {
     pool_worker(&j);
     return;
@@ -142,6 +162,8 @@ static void parallel_for(int nthreads, int64_t ntasks, task_fn fn, void *ctx) {
   pool_worker(&j);
   for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
 }
+
+#define parallel_for(nt, n, fn, ctx) parallel_for_named(#fn, nt, n, fn, ctx)
 
 /* ------------------------------------------------------------------ CSR builder */
 static int cmp_i32(const void *a, const void *b) {

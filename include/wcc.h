@@ -208,6 +208,18 @@ int wcc_cluster_csr(const wcc_csr *g, const int32_t *membership_in, int64_t *ncl
                     int64_t *nassigned, int64_t *nentries, int32_t *cl_ids, int64_t *cl_start,
                     int32_t *vert, int64_t *row_off, int32_t *adj, void *stream);
 
+/*
+ * wcc_ccr_components -- connected component refinement alone (Alg. 1, the first step of
+ * both WCC and CM): for every assigned vertex v, comp_out[v] = the smallest global id in
+ * v's connected component of the subgraph induced by v's cluster; -1 when v is
+ * unassigned.  No size gate is applied (a caller keeps components larger than s_pre).
+ *   g              device CSR (as for wcc_run)
+ *   membership_in  device, N int32 (negative = unassigned)
+ *   comp_out       device, N int32, caller-allocated
+ * Blocks until comp_out is complete.  Errors: WCC_EINVAL, WCC_ENOMEM, WCC_EHIP.
+ */
+int wcc_ccr_components(const wcc_csr *g, const int32_t *membership_in, int32_t *comp_out, void *stream);
+
 /* Threshold k(n) used by the library for the given criterion (host function). */
 int64_t wcc_threshold(int32_t criterion, int64_t n, int32_t lin_num, int32_t lin_den);
 

@@ -120,6 +120,8 @@ lib.wcc_server_wait.restype = ctypes.c_int
 lib.wcc_server_wait.argtypes = [_vp, _i64]
 lib.wcc_server_destroy.restype = ctypes.c_int
 lib.wcc_server_destroy.argtypes = [_vp]
+lib.wcc_ccr_components.restype = ctypes.c_int
+lib.wcc_ccr_components.argtypes = [ctypes.POINTER(Csr), _vp, _vp, _vp]
 lib.wcc_autotune.restype = ctypes.c_int
 lib.wcc_autotune.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(ExecConfig),
                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), _vp]
@@ -335,3 +337,16 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def ccr_components(offsets, indices, membership, out=None):
+    """Component of every vertex inside its cluster's induced subgraph (smallest global id;
+    -1 for unassigned vertices) as a device int32 tensor."""
+    import torch
+    g = make_csr(offsets, indices)
+    if out is None:
+        out = torch.empty_like(membership)
+    rc = lib.wcc_ccr_components(ctypes.byref(g), membership.data_ptr() if membership.numel() else None,
+                                out.data_ptr() if out.numel() else None, _stream(torch, membership.device))
+    _check(rc, "wcc_ccr_components")
+    return out

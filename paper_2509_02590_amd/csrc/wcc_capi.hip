@@ -1060,6 +1060,32 @@ int64_t est_workspace_bytes(int64_t N, int64_t nnz) {
   return b + b / 8 + 64 * 1024;
 }
 
+// CCR alone (Alg. 1): component labels of every cluster's induced subgraph.
+int ccr_impl(const wcc_csr *g, const int32_t *mem, int32_t *out, hipStream_t s) {
+  TRY(check_csr(g));
+  int64_t N = g->num_vertices;
+  if (N == 0) return WCC_OK;
+  if (!mem || !out) return WCC_EINVAL;
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  Workspace &w = *wp;
+  TRY(run_front(w, g, mem, false, false, false, s));
+  TRY(items_ccr_init(mem, N, out, s));
+  unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
+  TRY(prim_fill32(cnt, 0u, 2 * CNT_NUM, s));
+  FrontCounts fc;
+  TRY(read_counts(w, &fc, s));
+  wcc_params p;
+  wcc_default_params(&p);
+  ItemArgs A = base_args(w, p, (int32_t)(N + 1));
+  A.ccr_out = out;
+  int64_t lv = 0, launches = 0;
+  double ms = 0;
+  TRY(run_levels(w, A, fc.nitems, p.criterion, p, &lv, &ms, &launches, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return WCC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- served form
@@ -1231,6 +1257,15 @@ int wcc_mincut_split_batch(const wcc_csr *g, const int32_t *verts, const int64_t
     HIP_TRY(hipStreamSynchronize(s));
     if (nv < 0) return WCC_EINVAL;
     return split_batch_impl(g, verts, set_offsets, num_sets, caps, lambdas, sides, nv, s);
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int wcc_ccr_components(const wcc_csr *g, const int32_t *membership_in, int32_t *comp_out, void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    return ccr_impl(g, membership_in, comp_out, (hipStream_t)stream);
   } catch (...) {
     return WCC_ENOMEM;
   }

@@ -125,6 +125,9 @@ struct ItemArgs {
   int32_t *out_big_count;
   int32_t out_big_cap;
   int32_t small_max;
+  // CCR only: each vertex of a processed cluster gets the smallest global id of its
+  // component inside the cluster's induced subgraph (no cut, no children)
+  int32_t *ccr_out;
 };
 
 // ---------------------------------------------------------------- device helpers

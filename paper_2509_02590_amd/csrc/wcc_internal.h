@@ -45,6 +45,7 @@ int items_max_level();
 int64_t items_bitmap_words(int64_t n, int cap);
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s);
 int items_level_words();
+int items_ccr_init(const int32_t *mem, int64_t N, int32_t *out, hipStream_t s);
 int items_level_prep(int32_t *ctl, int nx, hipStream_t s);
 int items_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *nbig, const FrontCounts *fc,
                  int32_t g_nitems, int32_t g_nbig, int32_t g_top, ItemDesc *lstS, ItemDesc *lstB, int32_t *ctl,

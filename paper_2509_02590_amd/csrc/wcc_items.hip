@@ -788,6 +788,13 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     for (int e = threadIdx.x; e < s.m; e += IB) s.adj16[e] = (uint16_t)s.adjg[e];
   __syncthreads();
 
+  if (A.ccr_out) {
+    // components of the cluster's induced subgraph (Alg. 1), labelled by smallest member
+    item_cc(s, false, 0, sh);
+    for (int i = threadIdx.x; i < n; i += IB) A.ccr_out[ar.vtx[d.b + i]] = ar.vtx[d.b + ld(&s.B[i])];
+    __syncthreads();
+    return;
+  }
   if (A.split_only) {
     // mincut_split: disconnected -> 0 and the component of the first vertex
     int nc = item_cc(s, false, 0, sh);
@@ -991,6 +998,14 @@ __global__ void k_item_gather(const ItemDesc *in, const uint32_t *order, int32_t
   if (set_in) set_out[i] = set_in[order[i]];
 }
 
+// ---------------------------------------------------------------- CCR labels
+// Before the cluster items run: an assigned vertex is its own component (clusters with
+// no induced edge have no item), an unassigned one is -1.
+__global__ void k_ccr_init(const int32_t *mem, int64_t N, int32_t *out) {
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < N) out[v] = mem[v] >= 0 ? (int32_t)v : -1;
+}
+
 // ---------------------------------------------------------------- relabel
 __global__ void k_mark_mins(const int32_t *acc, int64_t N, int32_t *mark) {
   int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1043,6 +1058,13 @@ int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
 }
 
 int items_level_words() { return LV_WORDS; }
+
+int items_ccr_init(const int32_t *mem, int64_t N, int32_t *out, hipStream_t s) {
+  if (N <= 0) return WCC_OK;
+  hipLaunchKernelGGL(k_ccr_init, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, mem, N, out);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
 
 int items_level_prep(int32_t *ctl, int nx, hipStream_t s) {
   hipLaunchKernelGGL(k_level_prep, dim3(1), dim3(64), 0, s, ctl, nx);

@@ -219,3 +219,35 @@ def test_wcc_global_state_items(exec_mode):
             assert _rec_key(grec) == _rec_key(wrec)
     finally:
         w.set_exec_config()
+
+
+def _ccr_expected(off, adj, memb):
+    """Components of the intra-cluster graph by the oracle (smallest vertex; -1 unassigned)."""
+    n = len(memb)
+    off = np.asarray(off, np.int64)
+    src = np.repeat(np.arange(n), np.diff(off))
+    keep = (memb[src] >= 0) & (memb[src] == memb[adj])
+    off2 = np.concatenate([[0], np.cumsum(np.bincount(src[keep], minlength=n))]).astype(np.int64)
+    return oracle.components(off2, np.asarray(adj)[keep].astype(np.int32), alive=(memb >= 0))
+
+
+def test_ccr_components_match_oracle():
+    w = _w()
+    rng = np.random.default_rng(31)
+    cases = []
+    for trial in range(6):
+        n = int(rng.integers(50, 500))
+        memb = rng.integers(-1, 6, n).astype(np.int32) * 5 + 2
+        memb[memb < 0] = -1
+        edges = {(a, b) for a in range(n) for b in range(a + 1, n) if rng.random() < 0.02}
+        off, adj = csr_from_edges(n, sorted(edges))
+        cases.append((off, adj, memb))
+    g = gen.chung_lu(60000, 30.0, 2.5, 11, 2000, 2.0, 0.2, 0.15, 0.05, seed=78, intra_mult=1.8)
+    memb = g.membership.copy()
+    memb[::23] = -1
+    cases.append((g.offsets, g.indices, memb))
+    c0 = gen.c0()
+    cases.append((c0.offsets, c0.indices, c0.membership))
+    for off, adj, memb in cases:
+        got = w.ccr_components(_t(off, np.int32), _t(adj, np.int32), _t(memb, np.int32)).cpu().numpy()
+        assert np.array_equal(got, _ccr_expected(off, adj, memb))

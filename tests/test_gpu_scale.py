@@ -1,8 +1,13 @@
 """Parity at full size: the 10M-vertex / 200M-edge workload (clusters up to ~1e5 vertices,
-nested bridges).  The oracle cannot cut its largest clusters in reasonable time, so it
-runs on a random sample of whole input clusters (WCC treats clusters independently) and
-is compared set by set; every output set of the full run, largest clusters included, is
-checked for the properties the method guarantees at any size."""
+nested bridges) and, when WCC_TEST_C4=1, the 250M-vertex / 2B-edge workload (int64
+offsets, clusters up to ~1e6 vertices).  The oracle cannot cut their largest clusters in
+reasonable time, so it runs on a random sample of whole input clusters (WCC treats
+clusters independently) and is compared set by set; every output set of the full run,
+largest clusters included, is checked for the properties the method guarantees at any
+size.  The CM-style call (mincut_split_batch over every CCR component) is checked the
+same way on sampled sets."""
+import os
+
 import numpy as np
 import pytest
 
@@ -13,11 +18,30 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 torch = pytest.importorskip("torch")
 
+WORKLOADS = ["c2", pytest.param("c4", marks=pytest.mark.skipif(
+    os.environ.get("WCC_TEST_C4") != "1", reason="2B-edge workload: set WCC_TEST_C4=1 (needs ~60 GB host RAM)"))]
+
 
 def _dev():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch.device("cuda:0")
+
+
+_CACHE = {}
+
+
+def _workload(name):
+    if name not in _CACHE:
+        _CACHE.clear()
+        g = gen.c2() if name == "c2" else gen.c4()
+        dev = _dev()
+        ob = torch.int32 if g.indices.shape[0] < 2**31 else torch.int64
+        o = torch.from_numpy(g.offsets).to(dev).to(ob)
+        a = torch.from_numpy(g.indices).to(dev)
+        m = torch.from_numpy(g.membership).to(dev)
+        _CACHE[name] = (g, o, a, m)
+    return _CACHE[name]
 
 
 def _canon(labels, mask=None):
@@ -39,16 +63,46 @@ def _k_log10(n):
     return np.floor(np.log10(np.maximum(n, 1))).astype(np.int64) + 1  # exact for n < 1e15
 
 
-def test_c2_full_size_sampled_parity():
+def _sample_clusters(memb, seed, n_small=400, n_mid=4):
+    sizes = np.bincount(memb[memb >= 0])
+    rng = np.random.default_rng(seed)
+    ids = np.nonzero(sizes > 0)[0]
+    small = ids[sizes[ids] <= 3000]
+    mid = ids[(sizes[ids] > 3000) & (sizes[ids] <= 8000)]
+    return np.concatenate([rng.choice(small, min(n_small, len(small)), replace=False),
+                           rng.choice(mid, min(n_mid, len(mid)), replace=False)])
+
+
+def _label_graph(g, lab, chunk=200_000_000):
+    """CSR of the entries whose two ends carry the same label (>= 0), built row-chunk by
+    row-chunk so that 4e9-entry inputs stay within host memory."""
+    n = g.n
+    off = g.offsets
+    cnt = np.zeros(n, np.int64)
+    parts = []
+    r0 = 0
+    while r0 < n:
+        r1 = int(np.searchsorted(off, off[r0] + chunk, side="right")) - 1
+        r1 = max(r1, r0 + 1)
+        r1 = min(r1, n)
+        e0, e1 = off[r0], off[r1]
+        src = np.repeat(np.arange(r0, r1, dtype=np.int32), np.diff(off[r0:r1 + 1]))
+        dst = g.indices[e0:e1]
+        ls = lab[src]
+        keep = (ls >= 0) & (ls == lab[dst])
+        cnt[r0:r1] = np.bincount(src[keep] - r0, minlength=r1 - r0)
+        parts.append(dst[keep])
+        r0 = r1
+    off2 = np.zeros(n + 1, np.int64)
+    np.cumsum(cnt, out=off2[1:])
+    return off2, np.concatenate(parts) if parts else np.zeros(0, np.int32)
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_full_size_sampled_parity(name):
     import paper_2509_02590_amd as w
-    from scipy.sparse import csr_matrix
-    from scipy.sparse.csgraph import connected_components
-    g = gen.c2()
-    dev = _dev()
-    o = torch.from_numpy(g.offsets.astype(np.int32)).to(dev)
-    a = torch.from_numpy(g.indices).to(dev)
-    m = torch.from_numpy(g.membership).to(dev)
-    got, st, rec = w.wcc_run(o, a, m, records_cap=2_000_000)
+    g, o, a, m = _workload(name)
+    got, st, rec = w.wcc_run(o, a, m, records_cap=4_000_000)
     got = got.cpu().numpy()
     bat, _, _ = w.wcc_run(o, a, m, exec_mode="batched", graph=False)
     assert np.array_equal(bat.cpu().numpy(), got), "batched differs from plain"
@@ -57,38 +111,79 @@ def test_c2_full_size_sampled_parity():
     assert sizes.max() > 50_000  # the global-state path is exercised
 
     # 1) oracle on sampled whole clusters
-    rng = np.random.default_rng(20)
-    ids = np.nonzero(sizes > 0)[0]
-    small = ids[sizes[ids] <= 3000]
-    mid = ids[(sizes[ids] > 3000) & (sizes[ids] <= 8000)]
-    pick = np.concatenate([rng.choice(small, 400, replace=False), rng.choice(mid, 4, replace=False)])
+    pick = _sample_clusters(memb, 20)
     memb_s = np.where(np.isin(memb, pick), memb, -1).astype(np.int32)
     want, _ = oracle.wcc(g.offsets, g.indices, memb_s)
     mask = memb_s >= 0
     assert np.array_equal(_canon(got, mask), _canon(want)), "sampled clusters differ from the oracle"
 
     # 2) properties of every output set
-    lab = got.astype(np.int64)
+    lab = got.astype(np.int32)
     on = lab >= 0
     nsets = int(lab.max()) + 1
     assert nsets == st.accepted
     size = np.bincount(lab[on], minlength=nsets)
     assert size.min() > 10                                   # larger than s_post
-    rep = np.full(nsets, -1, np.int64)
-    rep[lab[on]] = np.nonzero(on)[0]
+    rep = np.full(nsets, np.iinfo(np.int64).max, np.int64)
+    np.minimum.at(rep, lab[on], np.nonzero(on)[0])         # smallest vertex of each set
     assert np.all(memb[on] == memb[rep[lab[on]]])            # inside one input cluster
-    deg = np.diff(g.offsets)
-    src = np.repeat(np.arange(g.n, dtype=np.int32), deg)
-    dst = g.indices
-    keep = on[src] & (lab[src] == lab[dst])
-    ks, kd = src[keep], dst[keep]
-    din = np.bincount(ks, minlength=g.n)
+    off2, adj2 = _label_graph(g, lab)
+    din = np.diff(off2)
     assert np.all(din[on] >= _k_log10(size[lab[on]]))        # KCORE: each set is a k(n)-core
-    sub = csr_matrix((np.ones(len(ks), np.int8), (ks, kd)), shape=(g.n, g.n))
-    ncomp, comp = connected_components(sub, directed=False)
-    assert len(np.unique(comp[on])) == nsets                 # each set connected, sets disjoint
-    # the cut records: every saved set has lambda >= k(n), every split set lambda < k(n)
-    r = rec
-    acc = r["lam"] >= r["k"]
+    comp = oracle.components(off2, adj2, alive=on.astype(np.uint8))
+    assert np.array_equal(np.unique(comp[on]).size, nsets)   # each set connected, sets disjoint
+    assert np.all(comp[on] == rep[lab[on]])                  # (component = labelled set)
+    # the cut records: accepted sets have lambda >= k(n); k(n) is the log10 rule
+    acc = rec["lam"] >= rec["k"]
     assert acc.sum() == st.accepted
-    assert np.all(r["k"] == _k_log10(r["n"]))
+    assert np.all(rec["k"] == _k_log10(rec["n"]))
+
+
+def _cm_sets(comp):
+    n = comp.numel()
+    lab = torch.where(comp >= 0, comp, torch.full_like(comp, n)).long()
+    size = torch.bincount(lab, minlength=n + 1)[:n]
+    keep = (comp >= 0) & (size[lab.clamp(max=n - 1)] > 10)
+    vid = torch.nonzero(keep).flatten()
+    order = torch.argsort(lab[vid], stable=True)
+    verts = vid[order].to(torch.int32).contiguous()
+    ksz = size[size > 10]
+    set_off = torch.zeros(ksz.numel() + 1, dtype=torch.int64, device=comp.device)
+    set_off[1:] = torch.cumsum(ksz, 0)
+    caps = torch.from_numpy(_k_log10(ksz.cpu().numpy()).astype(np.int32)).to(comp.device)
+    return verts, set_off, caps
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_cm_split_batch_full_size(name):
+    """CCR labels of sampled clusters and cuts of sampled CCR components, against the oracle."""
+    import paper_2509_02590_amd as w
+    g, o, a, m = _workload(name)
+    comp = w.ccr_components(o, a, m)
+    comp_h = comp.cpu().numpy()
+    memb = g.membership
+    pick = _sample_clusters(memb, 21, n_small=300, n_mid=2)
+    sel = np.isin(memb, pick)
+    deg = np.diff(g.offsets)
+    rows = np.nonzero(sel)[0]
+    # oracle components of the sampled clusters' intra-cluster graph
+    src = np.repeat(rows.astype(np.int64), deg[rows])
+    dst = np.concatenate([g.indices[g.offsets[v]:g.offsets[v + 1]] for v in rows]) if len(rows) else \
+        np.zeros(0, np.int32)
+    keep = memb[dst] == memb[src]
+    cnt = np.bincount(src[keep], minlength=g.n)
+    off2 = np.zeros(g.n + 1, np.int64)
+    np.cumsum(cnt, out=off2[1:])
+    want = oracle.components(off2, dst[keep].astype(np.int32), alive=sel.astype(np.uint8))
+    assert np.array_equal(np.where(sel, comp_h, -1), want)
+    verts, set_off, caps = _cm_sets(comp)
+    lam, side = w.mincut_split_batch(o, a, verts, set_off, caps)
+    lam, side = lam.cpu().numpy(), side.cpu().numpy().astype(bool)
+    so, vh, ch = set_off.cpu().numpy(), verts.cpu().numpy(), caps.cpu().numpy()
+    rng = np.random.default_rng(5)
+    small = np.nonzero(np.diff(so) <= 2000)[0]
+    for i in rng.choice(small, min(40, len(small)), replace=False):
+        vs = vh[so[i]:so[i + 1]]
+        wl, ws = oracle.mincut_split(g.offsets, g.indices, vs, int(ch[i]))
+        assert lam[i] == wl, i
+        assert np.array_equal(side[so[i]:so[i + 1]], ws), i
