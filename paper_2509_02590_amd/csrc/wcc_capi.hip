@@ -440,6 +440,9 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       (*launches)++;
     }
     (*levels)++;
+    if (env_int("WCC_VERBOSE", 0))
+      fprintf(stderr, "[wcc] level %lld: %d items (%d large, largest n=%d) -> %d children, %.1f ms\n",
+              (long long)*levels, nitems, nbig, top.n, nout, ms);
     if (nout > A.out_cap) return WCC_ENOMEM;
     long long errc = 0;
     HIP_TRY(hipMemcpyAsync(&errc, base.cnt + CNT_ERR, sizeof(errc), hipMemcpyDeviceToHost, s));
@@ -583,6 +586,8 @@ int finish_levels(Workspace &w, const ItemArgs &base, BatchPlan &pl, int *L, boo
     HIP_TRY(hipMemcpyAsync(&errc, base.cnt + CNT_ERR, sizeof(errc), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if ((long long)errc < 0) return (int)(long long)errc;
+    if (env_int("WCC_VERBOSE", 0))
+      fprintf(stderr, "[wcc] batched: %lld items left after %d levels\n", (long long)left, *L);
     if (left == 0) return WCC_OK;
     TRY(launch_levels(w, base, pl, *L, *L + LEVEL_CHUNK, timed, s));
     *L += LEVEL_CHUNK;

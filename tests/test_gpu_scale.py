@@ -93,6 +93,8 @@ def _label_graph(g, lab, chunk=200_000_000):
         cnt[r0:r1] = np.bincount(src[keep] - r0, minlength=r1 - r0)
         parts.append(dst[keep])
         r0 = r1
+        if len(off) > 50_000_000:
+            print("label graph: rows up to %d of %d" % (r0, n), flush=True)
     off2 = np.zeros(n + 1, np.int64)
     np.cumsum(cnt, out=off2[1:])
     return off2, np.concatenate(parts) if parts else np.zeros(0, np.int32)
@@ -104,7 +106,9 @@ def test_full_size_sampled_parity(name):
     g, o, a, m = _workload(name)
     got, st, rec = w.wcc_run(o, a, m, records_cap=4_000_000)
     got = got.cpu().numpy()
-    bat, _, _ = w.wcc_run(o, a, m, exec_mode="batched", graph=False)
+    print("%s plain: %.0f ms, %d sets" % (name, st.ms_total, st.accepted), flush=True)
+    bat, stb, _ = w.wcc_run(o, a, m, exec_mode="batched", graph=False)
+    print("%s batched: %.0f ms" % (name, stb.ms_total), flush=True)
     assert np.array_equal(bat.cpu().numpy(), got), "batched differs from plain"
     memb = g.membership
     sizes = np.bincount(memb[memb >= 0])
@@ -114,6 +118,7 @@ def test_full_size_sampled_parity(name):
     pick = _sample_clusters(memb, 20)
     memb_s = np.where(np.isin(memb, pick), memb, -1).astype(np.int32)
     want, _ = oracle.wcc(g.offsets, g.indices, memb_s)
+    print("oracle on %d sampled clusters done" % len(pick), flush=True)
     mask = memb_s >= 0
     assert np.array_equal(_canon(got, mask), _canon(want)), "sampled clusters differ from the oracle"
 
@@ -131,6 +136,7 @@ def test_full_size_sampled_parity(name):
     din = np.diff(off2)
     assert np.all(din[on] >= _k_log10(size[lab[on]]))        # KCORE: each set is a k(n)-core
     comp = oracle.components(off2, adj2, alive=on.astype(np.uint8))
+    print("components of the output sets done", flush=True)
     assert np.array_equal(np.unique(comp[on]).size, nsets)   # each set connected, sets disjoint
     assert np.all(comp[on] == rep[lab[on]])                  # (component = labelled set)
     # the cut records: accepted sets have lambda >= k(n); k(n) is the log10 rule
