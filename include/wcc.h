@@ -234,8 +234,8 @@ typedef struct {
   int32_t small_lds_kb; /* dynamic LDS of a small-bin workgroup, 4..64 KB (default 32) */
   int32_t wg_per_cu;    /* small-bin workgroups per CU; 0 = as many as the LDS allows, <= 8 */
   int32_t big_lds_kb;   /* dynamic LDS of a large-bin workgroup (one per CU), <= 159 KB */
-  int32_t big_max_pct;  /* BATCHED: most CUs (in percent) given to large-bin workgroups;
-                           0 = no large-bin launch (default 50) */
+  int32_t big_max_pct;  /* BATCHED: at most this share of the CUs (percent) runs
+                           large-bin workgroups; 0 = no large-bin launch (default 100) */
 } wcc_exec_config;
 
 /* Current shape (host out).  Environment variables WCC_LDS_KB, WCC_WG_PER_CU,

@@ -75,7 +75,7 @@ struct ExecCfg : wcc_exec_config {
     small_lds_kb = 32;
     wg_per_cu = 0;
     big_lds_kb = 159;
-    big_max_pct = 50;
+    big_max_pct = 100;
   }
 };
 bool cfg_valid(const wcc_exec_config &c) {
@@ -428,21 +428,21 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     int32_t nout = 0;
     HIP_TRY(hipMemcpyAsync(&nout, dcount, sizeof(nout), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    float ms = 0;
+    float ms_b = 0, ms_s = 0;
     if (nbig > 0) {
-      HIP_TRY(hipEventElapsedTime(&ms, w.evb0, w.evb1));
-      *ms_kernel += ms;
+      HIP_TRY(hipEventElapsedTime(&ms_b, w.evb0, w.evb1));
+      *ms_kernel += ms_b;
       (*launches)++;
     }
     if (nsmall > 0) {
-      HIP_TRY(hipEventElapsedTime(&ms, w.evs0, w.evs1));
-      *ms_kernel += ms;
+      HIP_TRY(hipEventElapsedTime(&ms_s, w.evs0, w.evs1));
+      *ms_kernel += ms_s;
       (*launches)++;
     }
     (*levels)++;
     if (env_int("WCC_VERBOSE", 0))
-      fprintf(stderr, "[wcc] level %lld: %d items (%d large, largest n=%d) -> %d children, %.1f ms\n",
-              (long long)*levels, nitems, nbig, top.n, nout, ms);
+      fprintf(stderr, "[wcc] level %lld: %d items (%d large, largest n=%d) -> %d children; large bin %.2f ms, "
+              "small bin %.2f ms\n", (long long)*levels, nitems, nbig, top.n, nout, ms_b, ms_s);
     if (nout > A.out_cap) return WCC_ENOMEM;
     long long errc = 0;
     HIP_TRY(hipMemcpyAsync(&errc, base.cnt + CNT_ERR, sizeof(errc), hipMemcpyDeviceToHost, s));
@@ -487,12 +487,15 @@ int plan_batched(Workspace &w, const wcc_params &p, int64_t N, int32_t nitems, B
     HIP_TRY(hipStreamSynchronize(s));
     pl->top_n = top.n;
   }
-  // with no large-bin launch every item stays in the small lists (large ones then run
-  // from global memory in small-bin workgroups)
-  pl->g_big = pl->nbig < shp.big_max ? pl->nbig : shp.big_max;
+  // Both bins are launched oversubscribed, as in the plain form: a workgroup leaves as soon
+  // as its list is empty, so CUs freed by one bin go to the other.  Large-bin workgroups:
+  // one per initial large item, at most the configured share of the CUs; with no
+  // large-bin launch every item stays in the small lists (large ones then run from
+  // global memory in small-bin workgroups).
+  int cap_big = shp.big_max;
+  pl->g_big = pl->nbig < cap_big ? pl->nbig : cap_big;
   if (pl->g_big == 0) pl->nbig = 0;
-  pl->g_small = (w.cus - pl->g_big) * shp.per_cu;
-  if (pl->g_small < 1) pl->g_small = 1;
+  pl->g_small = w.cus * shp.per_cu;
   int cap_top = (int)wcc_k_of(p.criterion, pl->top_n > 0 ? pl->top_n : 1, p.lin_num, p.lin_den);
   pl->gbits_words = items_bitmap_words(pl->top_n > 0 ? pl->top_n : 1, cap_top);
   // the items of one level are disjoint vertex sets; large ones have > small_max vertices
