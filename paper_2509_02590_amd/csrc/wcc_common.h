@@ -144,6 +144,14 @@ template <typename T>
 DEV T ld(const T *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Plain (cached) load for scratch that only this workgroup writes and that is read after
+// a barrier: all waves of a workgroup share one CU's vector L1, which stays coherent with
+// their own stores, so the value is current; unlike ld() the compiler may batch and
+// reorder these loads.
+template <typename T>
+DEV T ldr(const T *p) {
+  return *p;
+}
 template <typename T, typename U>
 DEV void st(T *p, U v) {
   __hip_atomic_store(p, (T)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

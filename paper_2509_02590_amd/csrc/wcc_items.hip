@@ -63,7 +63,7 @@ struct St {
   unsigned long long *prof_cnt; // segment timing slots (profiling runs only)
 };
 
-DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ld(&s.R[x + 1]) : s.m; }
+DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ldr(&s.R[x + 1]) : s.m; }
 
 // contraction marks: one bit per list entry in LDS when it fits, else one byte in global
 DEV void mark_set(const St &s, int e) {
@@ -119,18 +119,18 @@ DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
-      if (ld(&start[mid]) <= base) lo = mid;
+      if (ldr(&start[mid]) <= base) lo = mid;
       else hi = mid - 1;
     }
     int x = lo;
-    int xend = x + 1 < n ? ld(&start[x + 1]) : total;
+    int xend = x + 1 < n ? ldr(&start[x + 1]) : total;
 #pragma unroll
     for (int i = 0; i < CH; i++) {
       int e = base + i;
       if (e < total) {
         while (e >= xend) {
           x++;
-          xend = x + 1 < n ? ld(&start[x + 1]) : total;
+          xend = x + 1 < n ? ldr(&start[x + 1]) : total;
         }
         f(x, e, yv[i]);
       }
@@ -263,13 +263,13 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   for (int i = threadIdx.x; i < n; i += IB) st(&s.A[i], 0);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += IB) {
-    int L = ld(&s.B[i]);
+    int L = ldr(&s.B[i]);
     if (L >= 0) atomicAdd(&s.A[L], 1);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += IB) {
-    int L = ld(&s.B[i]);
-    if (L >= 0 && ld(&s.A[L]) <= gate) st(&s.B[i], -1);
+    int L = ldr(&s.B[i]);
+    if (L >= 0 && ldr(&s.A[L]) <= gate) st(&s.B[i], -1);
   }
   __syncthreads();
   // child starts: exclusive scan over representatives
@@ -277,7 +277,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   for (int base = 0; base < n; base += IB) {
     int i = base + threadIdx.x;
     int v = 0;
-    if (i < n && ld(&s.B[i]) == i) v = ld(&s.A[i]);
+    if (i < n && ldr(&s.B[i]) == i) v = ldr(&s.A[i]);
     int tot;
     int pre = block_excl_scan<IB>(v, sh.red, &tot);
     if (i < n) st(&s.D[i], carry + pre);
@@ -290,7 +290,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   if (threadIdx.x < 64) {
     for (int base = 0; base < n; base += 64) {
       int i = base + threadIdx.x;
-      int L = i < n ? ld(&s.B[i]) : -1;
+      int L = i < n ? ldr(&s.B[i]) : -1;
       uint64_t act = __ballot(L >= 0);
       while (act) {
         int leader = __ffsll((long long)act) - 1;
@@ -307,7 +307,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   __syncthreads();
   // D[L] now holds start + size; restore starts; clear new degrees and cursors
   for (int i = threadIdx.x; i < n; i += IB) {
-    if (ld(&s.B[i]) == i) st(&s.D[i], ld(&s.D[i]) - ld(&s.A[i]));
+    if (ldr(&s.B[i]) == i) st(&s.D[i], ldr(&s.D[i]) - ldr(&s.A[i]));
     if (i < K) {
       st(&s.C[i], 0);
       st(&s.F[i], 0);
@@ -316,15 +316,15 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   __syncthreads();
   // new degrees by new position (C); the rows are read from the arena
   for_entries(s.R, n, s.m, [&](int e) { return s.adjg[e]; }, [&](int i, int, int j) {
-    int L = ld(&s.B[i]);
-    if (L >= 0 && ld(&s.B[j]) == L) atomicAdd(&s.C[ld(&s.E[i])], 1);
+    int L = ldr(&s.B[i]);
+    if (L >= 0 && ldr(&s.B[j]) == L) atomicAdd(&s.C[ldr(&s.E[i])], 1);
   });
   __syncthreads();
   // row offsets by new position (exclusive scan of C, in place)
   long long ecarry = 0;
   for (int base = 0; base < K; base += IB) {
     int p = base + threadIdx.x;
-    long long v = p < K ? (long long)ld(&s.C[p]) : 0;
+    long long v = p < K ? (long long)ldr(&s.C[p]) : 0;
     long long tot;
     long long pre = block_excl_scan64<IB>(v, sh.red64, &tot);
     if (p < K) st(&s.C[p], (int)(ecarry + pre));
@@ -334,29 +334,32 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   __syncthreads();
   // vertex records of the children
   for (int i = threadIdx.x; i < n; i += IB) {
-    int L = ld(&s.B[i]);
+    int L = ldr(&s.B[i]);
     if (L < 0) continue;
-    int np = ld(&s.E[i]);
-    int o = ld(&s.C[np]);
-    int o1 = np + 1 < K ? ld(&s.C[np + 1]) : M;
+    int np = ldr(&s.E[i]);
+    int o = ldr(&s.C[np]);
+    int o1 = np + 1 < K ? ldr(&s.C[np + 1]) : M;
     nx.vtx[d.b + np] = ar.vtx[d.b + i];
     nx.rs[d.b + np] = d.eb + o;
     nx.rd[d.b + np] = o1 - o;
   }
   // rows: each kept entry takes the next slot of its row (order inside a row is free)
+  // (the slot is bounded by the row's counted length)
   for_entries(s.R, n, s.m, [&](int e) { return s.adjg[e]; }, [&](int i, int, int j) {
-    int L = ld(&s.B[i]);
-    if (L < 0 || ld(&s.B[j]) != L) return;
-    int np = ld(&s.E[i]);
+    int L = ldr(&s.B[i]);
+    if (L < 0 || ldr(&s.B[j]) != L) return;
+    int np = ldr(&s.E[i]);
+    int o = ldr(&s.C[np]);
+    int o1 = np + 1 < K ? ldr(&s.C[np + 1]) : M;
     int slot = atomicAdd(&s.F[np], 1);
-    nx.adj[d.eb + ld(&s.C[np]) + slot] = ld(&s.E[j]) - ld(&s.D[L]);
+    if (slot < o1 - o) nx.adj[d.eb + o + slot] = ldr(&s.E[j]) - ldr(&s.D[L]);
   });
   // descriptors of the children
   auto child = [&](int i) {
-    int cs = ld(&s.D[i]);
-    int sz = ld(&s.A[i]);
-    int o = ld(&s.C[cs]);
-    int o1 = cs + sz < K ? ld(&s.C[cs + sz]) : M;
+    int cs = ldr(&s.D[i]);
+    int sz = ldr(&s.A[i]);
+    int o = ldr(&s.C[cs]);
+    int o1 = cs + sz < K ? ldr(&s.C[cs + sz]) : M;
     ItemDesc c;
     c.b = d.b + cs;
     c.n = sz;
@@ -367,7 +370,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     return c;
   };
   for (int i = threadIdx.x; i < n; i += IB) {
-    if (ld(&s.B[i]) != i) continue;
+    if (ldr(&s.B[i]) != i) continue;
     ItemDesc c = child(i);
     atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * c.n + 4LL * c.m));
     if (A.out_big && c.n > A.small_max) {
@@ -480,8 +483,8 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     if (steps >= s.n) return -1;  // guard: a scan takes at most n steps
     steps++;
     int key = ld(&s.A[x]);
-    int e0 = ld(&stv[x]);
-    int cnt = ld(&lenv[x]);
+    int e0 = ldr(&stv[x]);
+    int cnt = ldr(&lenv[x]);
     uint64_t w0 = ld(&lvl0(s, jx)[x >> 6]);
     int top = key < bound ? key : bound;
     bool have0 = !list16 && x == cand;
@@ -504,8 +507,8 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     uint64_t rest = w0 & ~(1ull << (x & 63));
     cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
     if (!list16 && cand >= 0) {
-      int ce0 = ld(&stv[cand]);
-      int ccnt = ld(&lenv[cand]);
+      int ce0 = ldr(&stv[cand]);
+      int ccnt = ldr(&lenv[cand]);
       cand_y = lane < ccnt ? (coh ? ld(&list[ce0 + lane]) : list[ce0 + lane]) : -1;
     }
     SEG(2, "s_waitcnt lgkmcnt(0)")
@@ -559,7 +562,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   // Phase 0: minimum degree and its smallest vertex
   unsigned long long mv = ~0ull;
   for (int i = threadIdx.x; i < n; i += IB) {
-    unsigned long long dg = (unsigned long long)(uint32_t)(row_end(s, i) - ld(&s.R[i]));
+    unsigned long long dg = (unsigned long long)(uint32_t)(row_end(s, i) - ldr(&s.R[i]));
     unsigned long long v = (dg << 32) | (uint32_t)i;
     mv = v < mv ? v : mv;
   }
@@ -576,7 +579,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
     // super-vertex ids C; round 1 scans the item's own rows (starts R, lengths D)
     for (int i = threadIdx.x; i < n; i += IB) {
       st(&s.C[i], i);
-      st(&s.D[i], row_end(s, i) - ld(&s.R[i]));
+      st(&s.D[i], row_end(s, i) - ldr(&s.R[i]));
     }
     bool first = true;
     int total = s.m;  // entries in the current lists
@@ -593,7 +596,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       mark_clear(s, total);
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
-        if (ld(&s.C[x]) == x) bit_set(s, 0, x, sh.lcnt);
+        if (ldr(&s.C[x]) == x) bit_set(s, 0, x, sh.lcnt);
       __syncthreads();
       // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
       const int32_t *stv = first ? s.R : s.E;
@@ -644,7 +647,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       __syncthreads();
       int reps = 0;
       for (int v = threadIdx.x; v < n; v += IB) {
-        int c = ld(&s.A[ld(&s.B[ld(&s.C[v])])]);
+        int c = ldr(&s.A[ldr(&s.B[ldr(&s.C[v])])]);
         st(&s.C[v], c);
         reps += (c == v);
       }
@@ -656,8 +659,8 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       for (int x = threadIdx.x; x < n; x += IB) st(&s.D[x], 0);
       __syncthreads();
       for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
-        int a = ld(&s.C[v]);
-        if (ld(&s.C[u]) != a) atomicAdd(&s.D[a], 1);
+        int a = ldr(&s.C[v]);
+        if (ldr(&s.C[u]) != a) atomicAdd(&s.D[a], 1);
       });
       __syncthreads();
       int carry = 0;
@@ -675,17 +678,20 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       total = carry;
       __syncthreads();
       for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
-        int a = ld(&s.C[v]);
-        int bb = ld(&s.C[u]);
-        if (bb != a) st(&s.lists[atomicAdd(&s.A[a], 1)], bb);
+        int a = ldr(&s.C[v]);
+        int bb = ldr(&s.C[u]);
+        if (bb != a) {
+          int pos = atomicAdd(&s.A[a], 1);
+          if (pos < ldr(&s.E[a]) + ldr(&s.D[a])) st(&s.lists[pos], bb);  // within a's segment
+        }
       });
       __syncthreads();
       ph_mark(A, s, 6, &pt);
       // ---- degree check: smallest id of minimum weighted degree, strict improvement
       unsigned long long dm = ~0ull;
       for (int x = threadIdx.x; x < n; x += IB)
-        if (ld(&s.C[x]) == x) {
-          unsigned long long v = ((unsigned long long)(uint32_t)ld(&s.D[x]) << 32) | (uint32_t)x;
+        if (ldr(&s.C[x]) == x) {
+          unsigned long long v = ((unsigned long long)(uint32_t)ldr(&s.D[x]) << 32) | (uint32_t)x;
           dm = v < dm ? v : dm;
         }
       dm = block_min_u64<IB>(dm, sh.redu);
@@ -693,7 +699,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       if (dmin < bound) {
         bound = dmin;
         s_kind = 2;
-        for (int v = threadIdx.x; v < n; v += IB) st(&s.F[v], (int32_t)(ld(&s.C[v]) == xmin));
+        for (int v = threadIdx.x; v < n; v += IB) st(&s.F[v], (int32_t)(ldr(&s.C[v]) == xmin));
         __syncthreads();
         if (bound <= 1) break;
       }
@@ -731,7 +737,34 @@ DEV Geo item_geo(int n, long long m, int cap) {
 
 // LDS selects where the scan arrays live; instantiating both placements lets the
 // compiler emit LDS instructions (not generic ones) when they are in LDS.
-template <bool LDS>
+// Placement of the optional LDS arrays after the core (bitmaps and A, B, D, E, R): the
+// contraction mark bits, then the super-vertex ids C when `with_c`, then the 16-bit
+// adjacency copy.  The dispatcher and the item agree on it through this function.
+struct LdsPlan {
+  bool marks, adj;
+  long long c_off, adj_off;  // word offsets after the core
+};
+DEV LdsPlan lds_plan(const Geo &g, int n, long long lds_words, bool with_c) {
+  LdsPlan pl;
+  long long used = g.core;
+  pl.marks = used + g.marks <= lds_words;
+  if (pl.marks) used += g.marks;
+  pl.c_off = used - g.core;
+  if (with_c) used += n;
+  pl.adj_off = used - g.core;
+  pl.adj = pl.marks && used + g.adj <= lds_words;
+  return pl;
+}
+// C in LDS when it fits, unless that would cost the adjacency copy (read by every scan step)
+DEV bool want_c_in_lds(const Geo &g, int n, long long lds_words) {
+  if (g.core > lds_words) return false;
+  LdsPlan without = lds_plan(g, n, lds_words, false);
+  LdsPlan with = lds_plan(g, n, lds_words, true);
+  if (g.core + with.adj_off > lds_words) return false;  // C itself does not fit
+  return with.adj || !without.adj;
+}
+
+template <bool LDS, bool CL>
 DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int item_index, Sh &sh) {
   const Arena &ar = A.ar[d.depth & 1];
   int n = d.n;
@@ -760,9 +793,10 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     s.D = w + 2 * n;
     s.E = w + 3 * n;
     s.R = w + 4 * n;
-    s.markbits = nullptr;
-    if (g.core + g.marks <= A.lds_words) s.markbits = (uint32_t *)(w + 5 * n);
-    if (g.core + g.marks + g.adj <= A.lds_words) s.adj16 = (uint16_t *)(w + 5 * n + g.marks);
+    LdsPlan lp = lds_plan(g, n, A.lds_words, CL);
+    s.markbits = lp.marks ? (uint32_t *)(w + 5 * n) : nullptr;
+    if constexpr (CL) s.C = w + 5 * n + lp.c_off;
+    if (lp.adj) s.adj16 = (uint16_t *)(w + 5 * n + lp.adj_off);
   } else {
     s.bits = A.gbits + (size_t)blockIdx.x * A.gbits_words;
     if ((long long)g.lv * g.ls > A.gbits_words) {
@@ -909,8 +943,9 @@ DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int i
   int n = d.n;
   int cap = A.split_only ? A.split_cap[A.split_set[item_index]] : (int)wcc_k_of(A.crit, n, A.lin_num, A.lin_den);
   Geo g = item_geo(n, d.m, cap);
-  if (g.core <= A.lds_words) process_item_t<true>(A, d, dyn, item_index, sh);
-  else process_item_t<false>(A, d, dyn, item_index, sh);
+  if (g.core > A.lds_words) process_item_t<false, false>(A, d, dyn, item_index, sh);
+  else if (want_c_in_lds(g, n, A.lds_words)) process_item_t<true, true>(A, d, dyn, item_index, sh);
+  else process_item_t<true, false>(A, d, dyn, item_index, sh);
 }
 
 __global__ void __launch_bounds__(IB) k_items(ItemArgs A) {
