@@ -535,14 +535,17 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       }
     }
     SEG(4, "s_waitcnt lgkmcnt(0)")
-    int M = wave_max_i(bl);
+    // one reduction: (level + 1, 2^24 - 1 - id) packed, so the maximum is the highest
+    // raised level and, inside it, the smallest id (items have fewer than 2^24 vertices)
+    int P = wave_max_i(bl >= 0 ? ((bl + 1) << 24) | (0xFFFFFF - by) : 0);
+    int M = (P >> 24) - 1;
+    int pid = 0xFFFFFF - (P & 0xFFFFFF);
     int nx = -1;
     if (M > jx) {
-      nx = wave_min_i(bl == M ? by : 0x7fffffff);
+      nx = pid;
       jx = M;
     } else if (cand >= 0) {
-      int m = wave_min_i(bl == jx ? by : 0x7fffffff);
-      nx = m < cand ? m : cand;
+      nx = M == jx && pid < cand ? pid : cand;
     }
     x = nx;
     SEG(5, "s_waitcnt lgkmcnt(0)")
@@ -942,6 +945,10 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
 DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int item_index, Sh &sh) {
   int n = d.n;
   int cap = A.split_only ? A.split_cap[A.split_set[item_index]] : (int)wcc_k_of(A.crit, n, A.lin_num, A.lin_den);
+  if (n >= (1 << 24)) {  // ids of the scan's packed reduction
+    if (threadIdx.x == 0) err(A, WCC_EUNSUPPORTED);
+    return;
+  }
   Geo g = item_geo(n, d.m, cap);
   if (g.core > A.lds_words) process_item_t<false, false>(A, d, dyn, item_index, sh);
   else if (want_c_in_lds(g, n, A.lds_words)) process_item_t<true, true>(A, d, dyn, item_index, sh);
