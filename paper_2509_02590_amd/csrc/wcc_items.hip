@@ -59,6 +59,7 @@ struct St {
   int32_t *lists;              // global, entry-indexed crossing lists (rounds >= 2)
   int n, m;
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
+  bool l1;                     // summary level of the bitmaps kept (large items only)
   bool pf;                     // accumulate this item's phase profile
   unsigned long long *prof_cnt; // segment timing slots (profiling runs only)
 };
@@ -147,7 +148,7 @@ DEV uint64_t *lvl1(const St &s, int j) { return s.bits + (size_t)j * s.ls + s.nw
 // Setting and clearing need no returned values, so they never stall the scan.
 DEV void bit_set(const St &s, int j, int y, int *lcnt) {
   atomicOr((unsigned long long *)&lvl0(s, j)[y >> 6], 1ull << (y & 63));
-  atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
+  if (s.l1) atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
   atomicAdd(&lcnt[j], 1);
 }
 
@@ -174,6 +175,20 @@ DEV int bit_pick(const St &s, int bound, int *lcnt, int *j_out) {
   *j_out = j;
   uint64_t *L1 = lvl1(s, j);
   const uint64_t *L0 = lvl0(s, j);
+  if (!s.l1) {
+    // small items keep no summary: a wavefront reads 64 L0 words at a time
+    for (int c0 = 0; c0 < s.nw0; c0 += 64) {
+      uint64_t w0 = c0 + lane < s.nw0 ? ld(&L0[c0 + lane]) : 0ull;
+      uint64_t m0 = __ballot(w0 != 0);
+      if (m0) {
+        int b = __ffsll((long long)m0) - 1;
+        uint64_t wsel = readlane64(w0, b);
+        int x = (c0 + b) * 64 + __ffsll((long long)wsel) - 1;
+        return x < s.n ? x : -2;
+      }
+    }
+    return -2;
+  }
   for (int c0 = 0; c0 < s.nw1; c0 += 64) {
     uint64_t w1 = c0 + lane < s.nw1 ? ld(&L1[c0 + lane]) : 0ull;
     uint64_t m1 = __ballot(w1 != 0);
@@ -782,6 +797,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   s.nw1 = g.nw1;
   s.nw2 = g.nw2;
   s.ls = g.ls;
+  s.l1 = n > 16384;
   s.C = A.sC + d.b;
   s.F = A.sF + d.b;
   s.adjg = ar.adj + d.eb;
