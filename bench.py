@@ -233,7 +233,7 @@ def main():
         sys.exit(2)
     if args.workload == "served":
         # concurrent jobs need hardware queues of their own (HIP's default is 4)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+        os.environ["GPU_MAX_HW_QUEUES"] = "16"
         import torch
         import paper_2509_02590_amd as wcc
         served(args, wcc, torch)

@@ -64,7 +64,7 @@ enum BufId {
   B_VTX0, B_VTX1, B_RS0, B_RS1, B_RD0, B_RD1, B_ADJ0, B_ADJ1,
   B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SG, B_SEDGE, B_SMARK, B_GBITS,
   B_ITEMS0, B_ITEMS1, B_ITEMS_SORTED, B_SET0, B_SET_SORTED, B_IKEYS, B_IVALS, B_IKEYS2, B_IVALS2,
-  B_SPLITMEM, B_SMALL, B_LVCTL, B_LB0, B_LB1,
+  B_SPLITMEM, B_SMALL, B_LVCTL, B_LB0, B_LB1, B_LBS,
   B_NUM
 };
 
@@ -504,6 +504,7 @@ int plan_batched(Workspace &w, const wcc_params &p, int64_t N, int32_t nitems, B
   TRY(w.b[B_LVCTL].ensure((size_t)items_level_words() * 4));
   TRY(w.b[B_LB0].ensure((size_t)pl->capB * sizeof(ItemDesc)));
   TRY(w.b[B_LB1].ensure((size_t)pl->capB * sizeof(ItemDesc)));
+  TRY(w.b[B_LBS].ensure((size_t)pl->capB * sizeof(ItemDesc)));
   TRY(w.b[B_GBITS].ensure((size_t)(pl->g_big + pl->g_small) * pl->gbits_words * 8 + 64));
   return WCC_OK;
 }
@@ -542,10 +543,20 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
     A.small_max = pl.small_max;
     A.gbits_words = pl.gbits_words;
     if (pl.g_big > 0) {
+      // largest first (level 0 is sorted already) so that the longest items start at once;
+      // worth its launches only when the large list can hold thousands of items
+      ItemDesc *big_in = list_big(w, cur);
+      if (L > 0 && pl.capB >= 4096) {
+        TRY(items_sort_desc_dev(big_in, (int32_t)pl.capB, ctl + 2 * cur + 1, w.b[B_LBS].as<ItemDesc>(),
+                                w.b[B_IKEYS].as<uint32_t>(), w.b[B_IVALS].as<uint32_t>(),
+                                w.b[B_IKEYS2].as<uint32_t>(), w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p,
+                                w.b[B_TMP].bytes, s));
+        big_in = w.b[B_LBS].as<ItemDesc>();
+      }
       HIP_TRY(hipEventRecord(w.evf, s));
       HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
       ItemArgs Bg = A;
-      Bg.items = list_big(w, cur);
+      Bg.items = big_in;
       Bg.nitems_dev = ctl + 2 * cur + 1;
       Bg.nitems = (int32_t)pl.capB;
       Bg.next = ctl + items_level_words() - 1;

@@ -53,5 +53,7 @@ int items_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *nbig, co
 int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t *set_in, int32_t *set_out,
                     uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
                     hipStream_t s, int small_max, int32_t *nbig);
+int items_sort_desc_dev(const ItemDesc *in, int32_t cap, const int32_t *count, ItemDesc *out, uint32_t *k1,
+                        uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes, hipStream_t s);
 int items_relabel(const int32_t *acc, int64_t N, int32_t *mark, int32_t *rank, int32_t *out, void *tmp,
                   size_t tmp_bytes, hipStream_t s);

@@ -1048,6 +1048,17 @@ __global__ void k_item_keys(const ItemDesc *items, int32_t n, uint32_t *keys, ui
   vals[i] = (uint32_t)i;
   if (items[i].n > small_max) atomicAdd(nbig, 1);
 }
+// Keys of a largest-first sort of a list whose length is read on the device: entries
+// past the count get the largest key and sort last.
+__global__ void k_item_keys_dev(const ItemDesc *items, int32_t cap, const int32_t *count, uint32_t *keys,
+                                uint32_t *vals) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap) return;
+  int c = *count;
+  keys[i] = i < c ? 0x7fffffffu - (uint32_t)items[i].n : 0x7fffffffu;
+  vals[i] = (uint32_t)i;
+}
+
 __global__ void k_item_gather(const ItemDesc *in, const uint32_t *order, int32_t n, ItemDesc *out,
                               const int32_t *set_in, int32_t *set_out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1153,6 +1164,20 @@ int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t 
   if (rc) return rc;
   hipLaunchKernelGGL(k_item_gather, dim3((n + 255) / 256), dim3(256), 0, s, in, alt ? v2 : v1, n, out,
                      set_in, set_out);
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
+
+int items_sort_desc_dev(const ItemDesc *in, int32_t cap, const int32_t *count, ItemDesc *out, uint32_t *k1,
+                        uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes, hipStream_t s) {
+  if (cap <= 0) return WCC_OK;
+  hipLaunchKernelGGL(k_item_keys_dev, dim3((cap + 255) / 256), dim3(256), 0, s, in, cap, count, k1, v1);
+  HIP_TRY(hipGetLastError());
+  int alt = 0;
+  int rc = prim_radix_sort_pairs(k1, v1, k2, v2, cap, 31, tmp, tmp_bytes, s, &alt);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_item_gather, dim3((cap + 255) / 256), dim3(256), 0, s, in, alt ? v2 : v1, cap, out,
+                     (const int32_t *)nullptr, (int32_t *)nullptr);
   HIP_TRY(hipGetLastError());
   return WCC_OK;
 }
