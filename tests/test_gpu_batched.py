@@ -174,6 +174,14 @@ def test_batched_c1_full_matches_plain_and_oracle():
         torch.cuda.synchronize()
         assert np.array_equal(got.cpu().numpy(), want), it
     assert st.graph_replays == 1
+    # a small size-bin boundary: the large list can hold thousands of items and is sorted
+    # largest-first on the device at every level
+    try:
+        w.set_exec_config(small_lds_kb=4)
+        got, st, _ = w.wcc_run(o, a, m, exec_mode="batched", graph=False)
+        assert np.array_equal(got.cpu().numpy(), want)
+    finally:
+        w.set_exec_config()
 
 
 def test_autotune_picks_a_shape_and_caches_it(tmp_path, monkeypatch):
