@@ -400,6 +400,9 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     A.out_count = dcount;
     if (base.split_only) A.split_set = set_sorted;
     TRY(prim_fill32(dcount, 0u, 3, s));
+    // the large bin goes first on the caller's stream: its workgroups each need a whole
+    // CU's LDS and would otherwise wait for small-bin workgroups to drain; the small bin
+    // follows on the second stream
     HIP_TRY(hipEventRecord(w.evf, s));
     if (nbig > 0) {
       ItemArgs Bg = A;
@@ -407,11 +410,9 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       Bg.nitems = nbig;
       Bg.next = dnext_big;
       Bg.lds_words = (int32_t)(big_bytes / 4);
-      HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
-      HIP_TRY(hipEventRecord(w.evb0, w.s2));
-      TRY(items_launch(Bg, grid_big, big_bytes, w.s2));
-      HIP_TRY(hipEventRecord(w.evb1, w.s2));
-      HIP_TRY(hipEventRecord(w.evj, w.s2));
+      HIP_TRY(hipEventRecord(w.evb0, s));
+      TRY(items_launch(Bg, grid_big, big_bytes, s));
+      HIP_TRY(hipEventRecord(w.evb1, s));
     }
     if (nsmall > 0) {
       ItemArgs Sm = A;
@@ -420,11 +421,13 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       Sm.next = dnext;
       Sm.lds_words = (int32_t)(lds_bytes / 4);
       if (base.split_only) Sm.split_set = set_sorted + nbig;
-      HIP_TRY(hipEventRecord(w.evs0, s));
-      TRY(items_launch(Sm, grid_small, lds_bytes, s));
-      HIP_TRY(hipEventRecord(w.evs1, s));
+      HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
+      HIP_TRY(hipEventRecord(w.evs0, w.s2));
+      TRY(items_launch(Sm, grid_small, lds_bytes, w.s2));
+      HIP_TRY(hipEventRecord(w.evs1, w.s2));
+      HIP_TRY(hipEventRecord(w.evj, w.s2));
+      HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
     }
-    if (nbig > 0) HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
     int32_t nout = 0;
     HIP_TRY(hipMemcpyAsync(&nout, dcount, sizeof(nout), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -553,8 +556,8 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
                                 w.b[B_TMP].bytes, s));
         big_in = w.b[B_LBS].as<ItemDesc>();
       }
+      // large bin first on s, small bin on the second stream (see run_levels)
       HIP_TRY(hipEventRecord(w.evf, s));
-      HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
       ItemArgs Bg = A;
       Bg.items = big_in;
       Bg.nitems_dev = ctl + 2 * cur + 1;
@@ -562,10 +565,9 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
       Bg.next = ctl + items_level_words() - 1;
       Bg.lds_words = (int32_t)(pl.big_bytes / 4);
       Bg.gbits = gb;
-      if (t) HIP_TRY(hipEventRecord(w.lev[L][0], w.s2));
-      TRY(items_launch(Bg, pl.g_big, pl.big_bytes, w.s2));
-      if (t) HIP_TRY(hipEventRecord(w.lev[L][1], w.s2));
-      HIP_TRY(hipEventRecord(w.evj, w.s2));
+      if (t) HIP_TRY(hipEventRecord(w.lev[L][0], s));
+      TRY(items_launch(Bg, pl.g_big, pl.big_bytes, s));
+      if (t) HIP_TRY(hipEventRecord(w.lev[L][1], s));
     }
     ItemArgs Sm = A;
     Sm.items = list_small(w, cur);
@@ -574,10 +576,15 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
     Sm.next = ctl + items_level_words() - 2;
     Sm.lds_words = (int32_t)(pl.lds_bytes / 4);
     Sm.gbits = gb + (size_t)pl.g_big * pl.gbits_words;
-    if (t) HIP_TRY(hipEventRecord(w.lev[L][2], s));
-    TRY(items_launch(Sm, pl.g_small, pl.lds_bytes, s));
-    if (t) HIP_TRY(hipEventRecord(w.lev[L][3], s));
-    if (pl.g_big > 0) HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
+    hipStream_t ss = pl.g_big > 0 ? w.s2 : s;
+    if (pl.g_big > 0) HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
+    if (t) HIP_TRY(hipEventRecord(w.lev[L][2], ss));
+    TRY(items_launch(Sm, pl.g_small, pl.lds_bytes, ss));
+    if (t) HIP_TRY(hipEventRecord(w.lev[L][3], ss));
+    if (pl.g_big > 0) {
+      HIP_TRY(hipEventRecord(w.evj, w.s2));
+      HIP_TRY(hipStreamWaitEvent(s, w.evj, 0));
+    }
   }
   return WCC_OK;
 }
