@@ -461,8 +461,9 @@ DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *lc
 // [st[x], st[x]+len[x]) of `list` (LDS u16 when list16 != nullptr).  The contractible
 // entries form a forest plus extra edges: when a key first reaches the bound, the
 // scanned vertex becomes the parent (B) of the unscanned one; later contractible
-// entries are marked in s.mark.  coh: the list was written in this launch (read it past
-// the vector L1).  Returns the number of steps (< 0 on an inconsistency).
+// entries are marked in s.mark.  Lists of later rounds were written by this workgroup
+// before a barrier, so plain loads see them.  Returns the number of steps (< 0 on an
+// inconsistency).
 //
 // The next vertex usually follows from the step itself, without reading the bitmaps:
 // x was the smallest member of the highest non-empty level jx.  If this step raised some
@@ -510,7 +511,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     if (lane < cnt) {
       if (list16) y = list16[e0 + lane];
       else if (have0) y = cand_y;
-      else y = coh ? ld(&list[e0 + lane]) : list[e0 + lane];
+      else y = list[e0 + lane];
     }
     int nw = lane < cnt ? atomicAdd(&s.A[y], 1) + 1 : 0;
     // y is complete here; re-defining it in an empty asm statement keeps the compiler
@@ -524,7 +525,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     if (!list16 && cand >= 0) {
       int ce0 = ldr(&stv[cand]);
       int ccnt = ldr(&lenv[cand]);
-      cand_y = lane < ccnt ? (coh ? ld(&list[ce0 + lane]) : list[ce0 + lane]) : -1;
+      cand_y = lane < ccnt ? list[ce0 + lane] : -1;
     }
     SEG(2, "s_waitcnt lgkmcnt(0)")
     int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
@@ -538,7 +539,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         int e = base + 64 * k + lane;
-        yv[k] = e < cnt ? (list16 ? (int)list16[e0 + e] : (coh ? ld(&list[e0 + e]) : list[e0 + e])) : -1;
+        yv[k] = e < cnt ? (list16 ? (int)list16[e0 + e] : list[e0 + e]) : -1;
       }
 #pragma unroll
       for (int k = 0; k < 4; k++) {
