@@ -61,6 +61,7 @@ struct St {
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
   bool l1;                     // summary level of the bitmaps kept (large items only)
   bool pf;                     // accumulate this item's phase profile
+  bool seg;                    // and its scan segment timing (perturbs the scan)
   unsigned long long *prof_cnt; // segment timing slots (profiling runs only)
 };
 
@@ -71,9 +72,6 @@ DEV void mark_set(const St &s, int e) {
   if (s.markbits) atomicOr(&s.markbits[e >> 5], 1u << (e & 31));
   else st(&s.mark[e], 1);
 }
-DEV bool mark_get(const St &s, int e) {
-  return s.markbits ? ((ld(&s.markbits[e >> 5]) >> (e & 31)) & 1u) : ld(&s.mark[e]) != 0;
-}
 DEV void mark_clear(const St &s, int total) {
   if (s.markbits)
     for (int w = threadIdx.x; w < (total + 31) / 32; w += IB) st(&s.markbits[w], 0u);
@@ -81,6 +79,20 @@ DEV void mark_clear(const St &s, int total) {
     for (int e = threadIdx.x; e < total; e += IB) st(&s.mark[e], 0);
 }
 DEV int adj_at(const St &s, int e) { return s.adj16 ? (int)s.adj16[e] : s.adjg[e]; }
+
+// marks of the 16 entries [base, base + 16) below total as a bit mask (base % 16 == 0)
+DEV uint32_t mark_chunk(const St &s, int base, int total) {
+  uint32_t mk = 0;
+  if (s.markbits) {
+    mk = (ld(&s.markbits[base >> 5]) >> (base & 31)) & 0xFFFFu;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+      if (base + i < total && ld(&s.mark[base + i]) != 0) mk |= 1u << i;
+  }
+  if (total - base < 16) mk &= (1u << (total - base)) - 1u;
+  return mk;
+}
 
 DEV int uf_find(int32_t *P, int x) {
   for (;;) {
@@ -135,6 +147,78 @@ DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
         }
         f(x, e, yv[i]);
       }
+    }
+  }
+}
+
+// for_entries that leaves out the entries of owners x with skip(x): a chunk that lies
+// inside one skipped row is passed over without loading it.
+template <typename S, typename G, typename F>
+DEV void for_entries_skip(const int32_t *start, int n, int total, S skip, G get, F f) {
+  for (int base = threadIdx.x * CH; base < total; base += IB * CH) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (ldr(&start[mid]) <= base) lo = mid;
+      else hi = mid - 1;
+    }
+    int x = lo;
+    int xend = x + 1 < n ? ldr(&start[x + 1]) : total;
+    bool sk = skip(x);
+    // the chunk is passed over when every owner it touches is skipped
+    bool all = sk;
+    for (int z = x, zend = xend; all && zend < base + CH && zend < total;) {
+      z++;
+      zend = z + 1 < n ? ldr(&start[z + 1]) : total;
+      all = skip(z);
+    }
+    if (all) continue;
+    int yv[CH];
+#pragma unroll
+    for (int i = 0; i < CH; i++) yv[i] = base + i < total ? get(base + i) : 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) {
+      int e = base + i;
+      if (e < total) {
+        while (e >= xend) {
+          x++;
+          xend = x + 1 < n ? ldr(&start[x + 1]) : total;
+          sk = skip(x);
+        }
+        if (!sk) f(x, e, yv[i]);
+      }
+    }
+  }
+}
+
+// Calls f(x, e, y) for the marked entries e in [0, total) only (lists stored in ascending
+// owner order, as for for_entries); chunks without a mark are passed over unread.
+template <typename G, typename F>
+DEV void for_marked_entries(const St &s, const int32_t *start, int n, int total, G get, F f) {
+  static_assert(CH == 16, "mark_chunk reads 16 entries");
+  for (int base = threadIdx.x * CH; base < total; base += IB * CH) {
+    uint32_t mk = mark_chunk(s, base, total);
+    if (!mk) continue;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (ldr(&start[mid]) <= base) lo = mid;
+      else hi = mid - 1;
+    }
+    int x = lo;
+    int xend = x + 1 < n ? ldr(&start[x + 1]) : total;
+    int yv[CH];
+#pragma unroll
+    for (int i = 0; i < CH; i++) yv[i] = (mk >> i) & 1u ? get(base + i) : 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) {
+      if (!((mk >> i) & 1u)) continue;
+      int e = base + i;
+      while (e >= xend) {
+        x++;
+        xend = x + 1 < n ? ldr(&start[x + 1]) : total;
+      }
+      f(x, e, yv[i]);
     }
   }
 }
@@ -238,24 +322,77 @@ DEV void ph_mark(const ItemArgs &A, const St &s, int ph, unsigned long long *t) 
   *t = now;
 }
 
+// sub-phase profile: thread 0 adds the time since *t to CNT_PH slot `slot` (22..31)
+DEV void sub_mark(const St &s, int slot, unsigned long long *t) {
+  if (!s.pf || threadIdx.x != 0) return;
+  unsigned long long now = wall_clock64();
+  atomicAdd(&s.prof_cnt[slot - 16], now - *t);
+  *t = now;
+}
+
 DEV void err(const ItemArgs &A, int code) {
   atomicMin((long long *)&A.cnt[CNT_ERR], (long long)code);
 }
 
 // Connected components of the item restricted to alive vertices (alive = A[i] >= kmin
 // when use_deg, else all).  B[i] = smallest vertex of i's component, -1 if dead.
-// Returns the number of components.
+// Returns the number of components.  Uses E as scratch.
+//
+// Union-find with roots kept at the smallest id, in two passes over the edges (the
+// sampling scheme of Afforest, Sutton et al. 2018): first every alive vertex is united
+// with its first two alive neighbours, which already joins most of a connected item into
+// one tree; c = the root with the most members.  Then every edge is united from the side
+// of an endpoint that is not (yet) a child of c; an edge skipped from both sides joins two
+// members of c's tree, so the components are exact.  Rows of c's members are not read.
 DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   int n = s.n;
+  unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += IB) {
     bool al = !use_deg || ld(&s.A[i]) >= kmin;
     st(&s.B[i], al ? i : -1);
+    st(&s.E[i], 0);
   }
   __syncthreads();
-  for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int i, int, int j) {
-    if (j < i && ld(&s.B[i]) >= 0 && ld(&s.B[j]) >= 0) uf_unite(s.B, i, j);
-  });
+  for (int i = threadIdx.x; i < n; i += IB) {
+    if (ld(&s.B[i]) < 0) continue;
+    int r1 = row_end(s, i), found = 0;
+    for (int e = ldr(&s.R[i]); e < r1 && found < 2; e++) {
+      int j = adj_at(s, e);
+      if (ld(&s.B[j]) >= 0) {
+        uf_unite(s.B, i, j);
+        found++;
+      }
+    }
+  }
   __syncthreads();
+  sub_mark(s, 16, &q);
+  for (int i = threadIdx.x; i < n; i += IB) {
+    if (ld(&s.B[i]) < 0) continue;
+    int r = uf_find(s.B, i);
+    st(&s.B[i], r);
+    atomicAdd(&s.E[r], 1);
+  }
+  __syncthreads();
+  sub_mark(s, 17, &q);
+  unsigned long long best = ~0ull;
+  for (int i = threadIdx.x; i < n; i += IB) {
+    int c = ldr(&s.E[i]);
+    if (c > 0) {
+      unsigned long long v = ((unsigned long long)(uint32_t)(0x7fffffff - c) << 32) | (uint32_t)i;
+      best = v < best ? v : best;
+    }
+  }
+  best = block_min_u64<IB>(best, sh.redu);
+  const int cs = best == ~0ull ? -1 : (int)(best & 0xffffffffu);
+  sub_mark(s, 18, &q);
+  for_entries_skip(
+      s.R, n, s.m, [&](int x) { int b = ld(&s.B[x]); return b < 0 || b == cs; },
+      [&](int e) { return adj_at(s, e); },
+      [&](int i, int, int j) {
+        if (ld(&s.B[j]) >= 0) uf_unite(s.B, i, j);
+      });
+  __syncthreads();
+  sub_mark(s, 29, &q);
   int roots = 0;
   for (int i = threadIdx.x; i < n; i += IB) {
     if (ld(&s.B[i]) < 0) continue;
@@ -263,7 +400,9 @@ DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
     roots += (r == i);
     st(&s.B[i], r);
   }
-  return block_sum<IB>(roots, sh.red);  // includes barriers
+  int nr = block_sum<IB>(roots, sh.red);  // includes barriers
+  sub_mark(s, 30, &q);
+  return nr;
 }
 
 // ---------------------------------------------------------------- rebuild children
@@ -275,6 +414,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   const Arena &ar = A.ar[d.depth & 1];
   const Arena &nx = A.ar[(d.depth + 1) & 1];
   int n = s.n;
+  unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += IB) st(&s.A[i], 0);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += IB) {
@@ -301,6 +441,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   int K = carry;
   __syncthreads();
   if (K == 0) return;
+  sub_mark(s, 31, &q);
   // stable new positions: wave 0 walks the item in order (E[i] = new position)
   if (threadIdx.x < 64) {
     for (int base = 0; base < n; base += 64) {
@@ -471,15 +612,21 @@ DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *lc
 // the smallest of them.  Otherwise the top level stays jx and the next vertex is the
 // smaller of x's successor in its own bitmap word and the vertices raised to jx now;
 // when that successor does not exist, the bitmaps are searched.
+//
+// x's key equals jx (capped at the bound): x lies in level jx, and level jx + 1 is
+// empty.  The successor's list start, length and first 64 entries are loaded while the
+// current step runs, so a step that continues with the successor issues its first key
+// increments at once; only the bitmap word of x is read before them.
 DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
-                   const uint16_t *list16, bool coh, int bound, int *lcnt,
-                   unsigned long long *prof_hits) {
+                   const uint16_t *list16, int bound, int *lcnt, unsigned long long *prof_hits) {
   const int lane = threadIdx.x;
   int steps = 0, hits = 0;
-  int cand = -1, cand_y = -1;  // prefetched first 64 entries of the likely next vertex
-  int x = -1, jx = 0;          // next vertex when already known, and its level
+  int x = -1, jx = 0;      // next vertex when already known, and its level
+  bool have = false;       // x's list (start e0, length cnt, first 64 entries y0) is loaded
+  int e0 = 0, cnt = 0, y0 = -1;
   // optional segment timing of the largest item (profiling runs only)
-  const bool tm = prof_hits != nullptr && s.pf;
+  const bool tm = prof_hits != nullptr && s.pf && s.seg;
+  int picks = 0, longs = 0;
   unsigned long long tseg[7] = {0, 0, 0, 0, 0, 0, 0}, tl = 0;
 #define SEG(k, wait)                                                   \
   if (tm) {                                                            \
@@ -494,52 +641,53 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       x = bit_pick(s, bound, lcnt, &jx);
       if (x == -2) return -1;
       if (x < 0) break;
+      have = false;
+      picks++;
       SEG(0, "s_waitcnt lgkmcnt(0)")
     }
     if (steps >= s.n) return -1;  // guard: a scan takes at most n steps
     steps++;
-    int key = ld(&s.A[x]);
-    int e0 = ldr(&stv[x]);
-    int cnt = ldr(&lenv[x]);
+    hits += have;
     uint64_t w0 = ld(&lvl0(s, jx)[x >> 6]);
-    int top = key < bound ? key : bound;
-    bool have0 = !list16 && x == cand;
-    hits += have0;
-    // first 64 entries of x's list: from LDS, from the prefetch, or loaded now -- before
-    // the next prefetch is issued, so that waiting for them never waits for it
-    int y = -1;
-    if (lane < cnt) {
-      if (list16) y = list16[e0 + lane];
-      else if (have0) y = cand_y;
-      else y = list[e0 + lane];
-    }
-    int nw = lane < cnt ? atomicAdd(&s.A[y], 1) + 1 : 0;
-    // y is complete here; re-defining it in an empty asm statement keeps the compiler
-    // from waiting again (for the prefetch issued next) where y is used below
-    asm volatile("" : "+v"(y));
+    e0 = ldr(&stv[x]);
+    cnt = ldr(&lenv[x]);
+    int y = y0;
+    if (!have) y = lane < cnt ? (list16 ? (int)list16[e0 + lane] : list[e0 + lane]) : -1;
+    // first 64 increments; their results are used only after the successor's loads
+    // below have been issued
+    int old = -1;
+    if (lane < cnt) old = atomicAdd(&s.A[y], 1);
     SEG(1, "s_waitcnt vmcnt(0) lgkmcnt(0)")
-    if (lane == 0) st(&s.A[x], SCANNED);
-    if (lane <= top) bit_clear(s, lane, x, lcnt);
     uint64_t rest = w0 & ~(1ull << (x & 63));
-    cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
-    if (!list16 && cand >= 0) {
-      int ce0 = ldr(&stv[cand]);
-      int ccnt = ldr(&lenv[cand]);
-      cand_y = lane < ccnt ? list[ce0 + lane] : -1;
-    }
-    SEG(2, "s_waitcnt lgkmcnt(0)")
-    int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
-    // the first chunk is handled in its own straight-line block so that no wait for the
-    // prefetch in flight is placed in it
-    if (nw > 0) scan_entry(s, x, y, nw, e0 + lane, bound, lcnt, &bl, &by);
-    SEG(3, "s_waitcnt lgkmcnt(0)")
-    // longer lists: four chunks' loads are issued together, then processed in order
-    for (int base = 64; base < cnt; base += 256) {
-      int yv[4];
+    int cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
+    int cq = cand >= 0 ? cand : x;  // (x: a harmless in-range address)
+    int ce0 = ldr(&stv[cq]);
+    int ccnt = cand >= 0 ? ldr(&lenv[cq]) : 0;
+    if (lane == 0) st(&s.A[x], SCANNED);
+    if (lane <= jx) bit_clear(s, lane, x, lcnt);
+    // longer lists: the next 256 entries are loaded now as well
+    int yv[4] = {-1, -1, -1, -1};
+    longs += cnt > 64;
+    if (cnt > 64) {
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        int e = base + 64 * k + lane;
-        yv[k] = e < cnt ? (list16 ? (int)list16[e0 + e] : list[e0 + e]) : -1;
+        int e = 64 + 64 * k + lane;
+        if (e < cnt) yv[k] = list16 ? (int)list16[e0 + e] : list[e0 + e];
+      }
+    }
+    int cy = -1;
+    if (lane < ccnt) cy = list16 ? (int)list16[ce0 + lane] : list[ce0 + lane];
+    SEG(2, "s_waitcnt lgkmcnt(0)")
+    int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
+    if (old >= 0) scan_entry(s, x, y, old + 1, e0 + lane, bound, lcnt, &bl, &by);
+    SEG(3, "s_waitcnt lgkmcnt(0)")
+    for (int base = 64; base < cnt; base += 256) {
+      if (base > 64) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          int e = base + 64 * k + lane;
+          yv[k] = e < cnt ? (list16 ? (int)list16[e0 + e] : list[e0 + e]) : -1;
+        }
       }
 #pragma unroll
       for (int k = 0; k < 4; k++) {
@@ -563,11 +711,19 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     } else if (cand >= 0) {
       nx = M == jx && pid < cand ? pid : cand;
     }
+    have = nx >= 0 && nx == cand;
+    e0 = ce0;
+    cnt = ccnt;
+    y0 = cy;
     x = nx;
     SEG(5, "s_waitcnt lgkmcnt(0)")
   }
 #undef SEG
   if (prof_hits) *prof_hits += hits;
+  if (prof_hits && s.pf && lane == 0) {
+    atomicAdd(&s.prof_cnt[-3], (unsigned long long)picks);
+    atomicAdd(&s.prof_cnt[-2], (unsigned long long)longs);
+  }
   if (tm && lane == 0)
     for (int k = 0; k < 6; k++) atomicAdd(&s.prof_cnt[k], tseg[k]);
   return steps;
@@ -621,8 +777,8 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       const int32_t *stv = first ? s.R : s.E;
       if (threadIdx.x < 64) {
         unsigned long long hits = 0;
-        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, false, bound, sh.lcnt, &hits)
-                      : scan_round(s, stv, s.D, s.lists, nullptr, true, bound, sh.lcnt, &hits);
+        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, bound, sh.lcnt, &hits)
+                      : scan_round(s, stv, s.D, s.lists, nullptr, bound, sh.lcnt, &hits);
         if (s.pf && threadIdx.x == 0) {
           atomicAdd(&A.cnt[CNT_PH + 10], (unsigned long long)(r > 0 ? r : 0));
           atomicAdd(&A.cnt[CNT_PH + 11], hits);
@@ -640,6 +796,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       steps += sh.vi[3];
       ph_mark(A, s, 4, &pt);
       rounds++;
+      unsigned long long q = s.pf ? wall_clock64() : 0;
       // ---- contraction: parent forest, then unions of the extra marked entries; the new
       // id of a merged group is its smallest member (A serves as the group minimum)
       for (int x = threadIdx.x; x < n; x += IB)
@@ -648,15 +805,17 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
           st(&s.A[x], 0x7fffffff);
         }
       __syncthreads();
+      sub_mark(s, 22, &q);
+      // (B holds tree roots here, so most marked entries join one tree and stop at the check)
+      auto join = [&](int x, int, int y) {
+        if (ld(&s.B[x]) != ld(&s.B[y])) uf_unite(s.B, x, y);
+      };
       if (first)
-        for_entries(stv, n, total, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
-          if (mark_get(s, e)) uf_unite(s.B, x, y);
-        });
+        for_marked_entries(s, stv, n, total, [&](int e) { return adj_at(s, e); }, join);
       else
-        for_entries(stv, n, total, [&](int e) { return ld(&s.lists[e]); }, [&](int x, int e, int y) {
-          if (mark_get(s, e)) uf_unite(s.B, x, y);
-        });
+        for_marked_entries(s, stv, n, total, [&](int e) { return ldr(&s.lists[e]); }, join);
       __syncthreads();
+      sub_mark(s, 23, &q);
       for (int x = threadIdx.x; x < n; x += IB)
         if (ld(&s.C[x]) == x) {
           int r = uf_find(s.B, x);
@@ -664,6 +823,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
           atomicMin(&s.A[r], x);
         }
       __syncthreads();
+      sub_mark(s, 24, &q);
       int reps = 0;
       for (int v = threadIdx.x; v < n; v += IB) {
         int c = ldr(&s.A[ldr(&s.B[ldr(&s.C[v])])]);
@@ -671,17 +831,24 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
         reps += (c == v);
       }
       reps = block_sum<IB>(reps, sh.red);
+      sub_mark(s, 25, &q);
       ph_mark(A, s, 5, &pt);
       if (reps <= 1) break;
       first = false;
       // ---- crossing lists of the contracted graph (D = weighted degree, E = start)
+      // (the contraction marks are dead now: they flag the crossing entries instead)
       for (int x = threadIdx.x; x < n; x += IB) st(&s.D[x], 0);
+      mark_clear(s, s.m);
       __syncthreads();
-      for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
+      for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int e, int u) {
         int a = ldr(&s.C[v]);
-        if (ldr(&s.C[u]) != a) atomicAdd(&s.D[a], 1);
+        if (ldr(&s.C[u]) != a) {
+          atomicAdd(&s.D[a], 1);
+          mark_set(s, e);
+        }
       });
       __syncthreads();
+      sub_mark(s, 26, &q);
       int carry = 0;
       for (int base = 0; base < n; base += IB) {
         int x = base + threadIdx.x;
@@ -696,15 +863,15 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       }
       total = carry;
       __syncthreads();
-      for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
+      sub_mark(s, 27, &q);
+      for_marked_entries(s, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
         int a = ldr(&s.C[v]);
         int bb = ldr(&s.C[u]);
-        if (bb != a) {
-          int pos = atomicAdd(&s.A[a], 1);
-          if (pos < ldr(&s.E[a]) + ldr(&s.D[a])) st(&s.lists[pos], bb);  // within a's segment
-        }
+        int pos = atomicAdd(&s.A[a], 1);
+        if (pos < ldr(&s.E[a]) + ldr(&s.D[a])) st(&s.lists[pos], bb);  // within a's segment
       });
       __syncthreads();
+      sub_mark(s, 28, &q);
       ph_mark(A, s, 6, &pt);
       // ---- degree check: smallest id of minimum weighted degree, strict improvement
       unsigned long long dm = ~0ull;
@@ -831,7 +998,11 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     s.markbits = nullptr;
   }
   long long steps = 0, rounds = 0;
-  s.pf = A.prof == 1 || (A.prof == 2 && item_index == 0);
+  // profile: 1 every item, 2 (with scan segments) or 3 the first item of each launch,
+  // >= 1000 every item with at least that many vertices
+  s.pf = A.prof == 1 || ((A.prof == 2 || A.prof == 3) && item_index == 0) ||
+         (A.prof >= 1000 && n >= A.prof);
+  s.seg = A.prof == 2;
   s.prof_cnt = A.cnt + CNT_PH + 16;
   unsigned long long pt = s.pf ? wall_clock64() : 0;
   // every item reads its rows at least once: vtx, rs, rd per vertex and one index per entry
