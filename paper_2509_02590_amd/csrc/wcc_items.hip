@@ -43,7 +43,6 @@ struct Sh {
   int red[NW + 1];
   long long red64[NW + 1];
   unsigned long long redu[NW + 1];
-  int lcnt[64];                // members per scan level
   unsigned long long hsum;
   int vi[8];
 };
@@ -61,8 +60,7 @@ struct St {
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
   bool l1;                     // summary level of the bitmaps kept (large items only)
   bool pf;                     // accumulate this item's phase profile
-  bool seg;                    // and its scan segment timing (perturbs the scan)
-  unsigned long long *prof_cnt; // segment timing slots (profiling runs only)
+  unsigned long long *prof_cnt; // sub-phase timing slots (profiling runs only)
 };
 
 DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ldr(&s.R[x + 1]) : s.m; }
@@ -227,18 +225,16 @@ DEV void for_marked_entries(const St &s, const int32_t *start, int n, int total,
 DEV uint64_t *lvl0(const St &s, int j) { return s.bits + (size_t)j * s.ls; }
 DEV uint64_t *lvl1(const St &s, int j) { return s.bits + (size_t)j * s.ls + s.nw0; }
 
-// Level j: a bit per vertex (L0), a summary bit per L0 word that is set whenever a bit
-// of that word is set but only cleared lazily (L1), and the exact member count lcnt[j].
-// Setting and clearing need no returned values, so they never stall the scan.
-DEV void bit_set(const St &s, int j, int y, int *lcnt) {
+// Level j: a bit per vertex (L0) and, for large items, a summary bit per L0 word (L1)
+// that is set whenever a bit of that word is set but only cleared lazily.  Setting and
+// clearing need no returned values, so they never stall the scan.
+DEV void bit_set(const St &s, int j, int y) {
   atomicOr((unsigned long long *)&lvl0(s, j)[y >> 6], 1ull << (y & 63));
   if (s.l1) atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
-  atomicAdd(&lcnt[j], 1);
 }
 
-DEV void bit_clear(const St &s, int j, int x, int *lcnt) {
+DEV void bit_clear(const St &s, int j, int x) {
   atomicAnd((unsigned long long *)&lvl0(s, j)[x >> 6], ~(1ull << (x & 63)));
-  atomicSub(&lcnt[j], 1);
 }
 
 DEV uint64_t readlane64(uint64_t v, int l) {
@@ -246,17 +242,11 @@ DEV uint64_t readlane64(uint64_t v, int l) {
          (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
 }
 
-// Wavefront-cooperative pick: the smallest id in the highest non-empty level, -1 when
-// every super-vertex is scanned, -2 on an inconsistent bitmap.  All lanes return it;
-// *j_out receives its level.  Summary words whose L0 words all turned empty are reset.
-DEV int bit_pick(const St &s, int bound, int *lcnt, int *j_out) {
+// Wavefront-cooperative search of level j: its smallest member, -1 when it is empty, -2
+// on an inconsistent bitmap.  All lanes return it.  Summary words whose L0 words all
+// turned empty are reset.
+DEV int level_first(const St &s, int j) {
   const int lane = __lane_id();
-  *j_out = 0;
-  int c = lane <= bound ? ld(&lcnt[lane]) : 0;
-  uint64_t nz = __ballot(c > 0);
-  if (!nz) return -1;
-  int j = 63 - __clzll(nz);
-  *j_out = j;
   uint64_t *L1 = lvl1(s, j);
   const uint64_t *L0 = lvl0(s, j);
   if (!s.l1) {
@@ -271,7 +261,7 @@ DEV int bit_pick(const St &s, int bound, int *lcnt, int *j_out) {
         return x < s.n ? x : -2;
       }
     }
-    return -2;
+    return -1;
   }
   for (int c0 = 0; c0 < s.nw1; c0 += 64) {
     uint64_t w1 = c0 + lane < s.nw1 ? ld(&L1[c0 + lane]) : 0ull;
@@ -292,7 +282,22 @@ DEV int bit_pick(const St &s, int bound, int *lcnt, int *j_out) {
       m1 &= m1 - 1;
     }
   }
-  return -2;
+  return -1;
+}
+
+// The smallest id in the highest non-empty level, searching down from *j (every level
+// above *j is empty); -1 when every super-vertex is scanned, -2 on an inconsistency.
+// *j receives the level found.
+DEV int bit_pick(const St &s, int *j) {
+  for (int l = *j; l >= 0; l--) {
+    int x = level_first(s, l);
+    if (x != -1) {
+      *j = l;
+      return x;
+    }
+  }
+  *j = 0;
+  return -1;
 }
 
 // Wavefront reductions without the LDS crossbar: DPP exchanges inside each row of 16
@@ -586,10 +591,9 @@ DEV int item_peel(const St &s, int k, Sh &sh) {
 constexpr int32_t SCANNED = -(1 << 30);  // key of a scanned super-vertex (stays negative)
 
 // Effect of one list entry x -> y whose increment left y's key at nw > 0.
-DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *lcnt,
-                    int *bl, int *by) {
+DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *bl, int *by) {
   int lv = nw < bound ? nw : bound;
-  if (nw <= bound) bit_set(s, nw, y, lcnt);
+  if (nw <= bound) bit_set(s, nw, y);
   if (nw == bound) st(&s.B[y], x);          // contractible, first for y: parent
   else if (nw > bound) mark_set(s, e);      // contractible, extra edge
   if (lv > *bl || (lv == *bl && y < *by)) {
@@ -599,94 +603,81 @@ DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *lc
 }
 
 // One round's maximum-adjacency scan, run by wave 0.  Lists: owner x's entries are
-// [st[x], st[x]+len[x]) of `list` (LDS u16 when list16 != nullptr).  The contractible
-// entries form a forest plus extra edges: when a key first reaches the bound, the
-// scanned vertex becomes the parent (B) of the unscanned one; later contractible
-// entries are marked in s.mark.  Lists of later rounds were written by this workgroup
-// before a barrier, so plain loads see them.  Returns the number of steps (< 0 on an
-// inconsistency).
+// [st[x], st[x]+len[x]) of `list` (LDS u16 when L16).  The contractible entries form a
+// forest plus extra edges: when a key first reaches the bound, the scanned vertex becomes
+// the parent (B) of the unscanned one; later contractible entries are marked in s.mark.
+// Lists of later rounds were written by this workgroup before a barrier, so plain loads
+// see them.  Returns the number of steps (< 0 on an inconsistency).
 //
 // The next vertex usually follows from the step itself, without reading the bitmaps:
 // x was the smallest member of the highest non-empty level jx.  If this step raised some
 // keys above jx, the new top level holds exactly those vertices, and the next vertex is
 // the smallest of them.  Otherwise the top level stays jx and the next vertex is the
 // smaller of x's successor in its own bitmap word and the vertices raised to jx now;
-// when that successor does not exist, the bitmaps are searched.
+// when that successor does not exist, the bitmaps are searched from level jx down
+// (every level above jx is empty then).
 //
 // x's key equals jx (capped at the bound): x lies in level jx, and level jx + 1 is
 // empty.  The successor's list start, length and first 64 entries are loaded while the
 // current step runs, so a step that continues with the successor issues its first key
 // increments at once; only the bitmap word of x is read before them.
+template <bool L16>
 DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
-                   const uint16_t *list16, int bound, int *lcnt, unsigned long long *prof_hits) {
+                   const uint16_t *list16, int bound) {
   const int lane = threadIdx.x;
-  int steps = 0, hits = 0;
+  auto entry = [&](int e) -> int {
+    if constexpr (L16) return (int)list16[e];
+    else return list[e];
+  };
+  int steps = 0;
   int x = -1, jx = 0;      // next vertex when already known, and its level
   bool have = false;       // x's list (start e0, length cnt, first 64 entries y0) is loaded
   int e0 = 0, cnt = 0, y0 = -1;
-  // optional segment timing of the largest item (profiling runs only)
-  const bool tm = prof_hits != nullptr && s.pf && s.seg;
-  int picks = 0, longs = 0;
-  unsigned long long tseg[7] = {0, 0, 0, 0, 0, 0, 0}, tl = 0;
-#define SEG(k, wait)                                                   \
-  if (tm) {                                                            \
-    asm volatile(wait ::: "memory");                                   \
-    unsigned long long tn = wall_clock64();                            \
-    tseg[k] += tn - tl;                                                \
-    tl = tn;                                                           \
-  }
-  if (tm) tl = wall_clock64();
   for (;;) {
     if (x < 0) {
-      x = bit_pick(s, bound, lcnt, &jx);
+      x = __builtin_amdgcn_readfirstlane(bit_pick(s, &jx));
+      jx = __builtin_amdgcn_readfirstlane(jx);
       if (x == -2) return -1;
       if (x < 0) break;
       have = false;
-      picks++;
-      SEG(0, "s_waitcnt lgkmcnt(0)")
     }
     if (steps >= s.n) return -1;  // guard: a scan takes at most n steps
     steps++;
-    hits += have;
     uint64_t w0 = ld(&lvl0(s, jx)[x >> 6]);
     e0 = ldr(&stv[x]);
     cnt = ldr(&lenv[x]);
     int y = y0;
-    if (!have) y = lane < cnt ? (list16 ? (int)list16[e0 + lane] : list[e0 + lane]) : -1;
+    if (!have) y = lane < cnt ? entry(e0 + lane) : -1;
     // first 64 increments; their results are used only after the successor's loads
     // below have been issued
     int old = -1;
     if (lane < cnt) old = atomicAdd(&s.A[y], 1);
-    SEG(1, "s_waitcnt vmcnt(0) lgkmcnt(0)")
     uint64_t rest = w0 & ~(1ull << (x & 63));
     int cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
     int cq = cand >= 0 ? cand : x;  // (x: a harmless in-range address)
     int ce0 = ldr(&stv[cq]);
     int ccnt = cand >= 0 ? ldr(&lenv[cq]) : 0;
     if (lane == 0) st(&s.A[x], SCANNED);
-    if (lane <= jx) bit_clear(s, lane, x, lcnt);
+    if (lane <= jx) bit_clear(s, lane, x);
     // longer lists: the next 256 entries are loaded now as well
     int yv[4] = {-1, -1, -1, -1};
-    longs += cnt > 64;
     if (cnt > 64) {
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         int e = 64 + 64 * k + lane;
-        if (e < cnt) yv[k] = list16 ? (int)list16[e0 + e] : list[e0 + e];
+        if (e < cnt) yv[k] = entry(e0 + e);
       }
     }
     int cy = -1;
-    if (lane < ccnt) cy = list16 ? (int)list16[ce0 + lane] : list[ce0 + lane];
-    SEG(2, "s_waitcnt lgkmcnt(0)")
+    if (lane < ccnt) cy = entry(ce0 + lane);
     int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
-    if (old >= 0) scan_entry(s, x, y, old + 1, e0 + lane, bound, lcnt, &bl, &by);
-    SEG(3, "s_waitcnt lgkmcnt(0)")
+    if (old >= 0) scan_entry(s, x, y, old + 1, e0 + lane, bound, &bl, &by);
     for (int base = 64; base < cnt; base += 256) {
       if (base > 64) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           int e = base + 64 * k + lane;
-          yv[k] = e < cnt ? (list16 ? (int)list16[e0 + e] : list[e0 + e]) : -1;
+          yv[k] = e < cnt ? entry(e0 + e) : -1;
         }
       }
 #pragma unroll
@@ -694,11 +685,10 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
         int e = base + 64 * k + lane;
         if (e < cnt) {
           int nw2 = atomicAdd(&s.A[yv[k]], 1) + 1;
-          if (nw2 > 0) scan_entry(s, x, yv[k], nw2, e0 + e, bound, lcnt, &bl, &by);
+          if (nw2 > 0) scan_entry(s, x, yv[k], nw2, e0 + e, bound, &bl, &by);
         }
       }
     }
-    SEG(4, "s_waitcnt lgkmcnt(0)")
     // one reduction: (level + 1, 2^24 - 1 - id) packed, so the maximum is the highest
     // raised level and, inside it, the smallest id (items have fewer than 2^24 vertices)
     int P = wave_max_i(bl >= 0 ? ((bl + 1) << 24) | (0xFFFFFF - by) : 0);
@@ -715,17 +705,10 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     e0 = ce0;
     cnt = ccnt;
     y0 = cy;
-    x = nx;
-    SEG(5, "s_waitcnt lgkmcnt(0)")
+    // (uniform: kept in scalar registers)
+    x = __builtin_amdgcn_readfirstlane(nx);
+    jx = __builtin_amdgcn_readfirstlane(jx);
   }
-#undef SEG
-  if (prof_hits) *prof_hits += hits;
-  if (prof_hits && s.pf && lane == 0) {
-    atomicAdd(&s.prof_cnt[-3], (unsigned long long)picks);
-    atomicAdd(&s.prof_cnt[-2], (unsigned long long)longs);
-  }
-  if (tm && lane == 0)
-    for (int k = 0; k < 6; k++) atomicAdd(&s.prof_cnt[k], tseg[k]);
   return steps;
 }
 
@@ -763,7 +746,6 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       // ---- round setup: keys, marks, bitmaps (levels 0..bound)
       int words = (bound + 1) * s.ls;
       for (int w = threadIdx.x; w < words; w += IB) st(&s.bits[w], (uint64_t)0);
-      if (threadIdx.x < 64) sh.lcnt[threadIdx.x] = 0;
       for (int x = threadIdx.x; x < n; x += IB) {
         st(&s.A[x], 0);
         st(&s.B[x], x);
@@ -771,17 +753,16 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       mark_clear(s, total);
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += IB)
-        if (ldr(&s.C[x]) == x) bit_set(s, 0, x, sh.lcnt);
+        if (ldr(&s.C[x]) == x) bit_set(s, 0, x);
       __syncthreads();
       // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
       const int32_t *stv = first ? s.R : s.E;
       if (threadIdx.x < 64) {
-        unsigned long long hits = 0;
-        int r = first ? scan_round(s, stv, s.D, s.adjg, s.adj16, bound, sh.lcnt, &hits)
-                      : scan_round(s, stv, s.D, s.lists, nullptr, bound, sh.lcnt, &hits);
+        int r = !first    ? scan_round<false>(s, stv, s.D, s.lists, nullptr, bound)
+                : s.adj16 ? scan_round<true>(s, stv, s.D, nullptr, s.adj16, bound)
+                          : scan_round<false>(s, stv, s.D, s.adjg, nullptr, bound);
         if (s.pf && threadIdx.x == 0) {
           atomicAdd(&A.cnt[CNT_PH + 10], (unsigned long long)(r > 0 ? r : 0));
-          atomicAdd(&A.cnt[CNT_PH + 11], hits);
           atomicAdd(&A.cnt[CNT_PH + 12], 1ull);
         }
         if (threadIdx.x == 0) sh.vi[3] = r;
@@ -998,11 +979,10 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     s.markbits = nullptr;
   }
   long long steps = 0, rounds = 0;
-  // profile: 1 every item, 2 (with scan segments) or 3 the first item of each launch,
-  // >= 1000 every item with at least that many vertices
-  s.pf = A.prof == 1 || ((A.prof == 2 || A.prof == 3) && item_index == 0) ||
+  // profile: 1 every item, 2 the first item of each launch, >= 1000 every item with at
+  // least that many vertices
+  s.pf = A.prof == 1 || (A.prof == 2 && item_index == 0) ||
          (A.prof >= 1000 && n >= A.prof);
-  s.seg = A.prof == 2;
   s.prof_cnt = A.cnt + CNT_PH + 16;
   unsigned long long pt = s.pf ? wall_clock64() : 0;
   // every item reads its rows at least once: vtx, rs, rd per vertex and one index per entry
