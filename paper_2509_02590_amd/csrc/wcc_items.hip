@@ -222,8 +222,9 @@ DEV void for_marked_entries(const St &s, const int32_t *start, int n, int total,
 }
 
 // ---------------------------------------------------------------- bitmap levels
-DEV uint64_t *lvl0(const St &s, int j) { return s.bits + (size_t)j * s.ls; }
-DEV uint64_t *lvl1(const St &s, int j) { return s.bits + (size_t)j * s.ls + s.nw0; }
+// (level j < 64 and ls < 2^24: a 24-bit multiply)
+DEV uint64_t *lvl0(const St &s, int j) { return s.bits + __umul24((unsigned)j, (unsigned)s.ls); }
+DEV uint64_t *lvl1(const St &s, int j) { return s.bits + __umul24((unsigned)j, (unsigned)s.ls) + s.nw0; }
 
 // Level j: a bit per vertex (L0) and, for large items, a summary bit per L0 word (L1)
 // that is set whenever a bit of that word is set but only cleared lazily.  Setting and
@@ -689,17 +690,20 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
         }
       }
     }
-    // one reduction: (level + 1, 2^24 - 1 - id) packed, so the maximum is the highest
-    // raised level and, inside it, the smallest id (items have fewer than 2^24 vertices)
-    int P = wave_max_i(bl >= 0 ? ((bl + 1) << 24) | (0xFFFFFF - by) : 0);
-    int M = (P >> 24) - 1;
-    int pid = 0xFFFFFF - (P & 0xFFFFFF);
-    int nx = -1;
-    if (M > jx) {
-      nx = pid;
-      jx = M;
-    } else if (cand >= 0) {
-      nx = M == jx && pid < cand ? pid : cand;
+    // only keys raised to jx or above can decide the next vertex; when there are any, one
+    // reduction of (level + 1, 2^24 - 1 - id) packed finds the highest raised level and,
+    // inside it, the smallest id (items have fewer than 2^24 vertices)
+    int nx = cand;
+    if (__ballot(bl >= jx)) {
+      int P = wave_max_i(bl >= jx ? ((bl + 1) << 24) | (0xFFFFFF - by) : 0);
+      int M = (P >> 24) - 1;
+      int pid = 0xFFFFFF - (P & 0xFFFFFF);
+      if (M > jx) {
+        nx = pid;
+        jx = M;
+      } else if (cand >= 0 && pid < cand) {
+        nx = pid;
+      }
     }
     have = nx >= 0 && nx == cand;
     e0 = ce0;
