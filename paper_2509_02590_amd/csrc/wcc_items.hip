@@ -630,10 +630,15 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     if constexpr (L16) return (int)list16[e];
     else return list[e];
   };
+  // uniform state in scalar registers; this lane's bitmap level offset for clearing
+  const int n = __builtin_amdgcn_readfirstlane(s.n);
+  const unsigned ls = (unsigned)__builtin_amdgcn_readfirstlane(s.ls);
+  bound = __builtin_amdgcn_readfirstlane(bound);
+  const unsigned my_lv = __umul24((unsigned)(lane <= bound ? lane : bound), ls);
   int steps = 0;
   int x = -1, jx = 0;      // next vertex when already known, and its level
-  bool have = false;       // x's list (start e0, length cnt, first 64 entries y0) is loaded
-  int e0 = 0, cnt = 0, y0 = -1;
+  bool have = false;       // x's list (start e0, length cnt, first 64 entries y) is loaded
+  int e0 = 0, cnt = 0, y = -1;
   for (;;) {
     if (x < 0) {
       x = __builtin_amdgcn_readfirstlane(bit_pick(s, &jx));
@@ -642,51 +647,59 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       if (x < 0) break;
       have = false;
     }
-    if (steps >= s.n) return -1;  // guard: a scan takes at most n steps
+    if (steps >= n) return -1;  // guard: a scan takes at most n steps
     steps++;
-    uint64_t w0 = ld(&lvl0(s, jx)[x >> 6]);
-    e0 = ldr(&stv[x]);
-    cnt = ldr(&lenv[x]);
-    int y = y0;
-    if (!have) y = lane < cnt ? entry(e0 + lane) : -1;
+    const int xw = x >> 6;
+    const uint64_t xbit = 1ull << (x & 63);
+    uint64_t w0 = ld(&s.bits[__umul24((unsigned)jx, ls) + xw]);
+    if (!have) {
+      e0 = ldr(&stv[x]);
+      cnt = ldr(&lenv[x]);
+      y = lane < cnt ? entry(e0 + lane) : -1;
+    }
     // first 64 increments; their results are used only after the successor's loads
     // below have been issued
     int old = -1;
     if (lane < cnt) old = atomicAdd(&s.A[y], 1);
-    uint64_t rest = w0 & ~(1ull << (x & 63));
+    uint64_t rest = w0 & ~xbit;
     int cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
-    int cq = cand >= 0 ? cand : x;  // (x: a harmless in-range address)
-    int ce0 = ldr(&stv[cq]);
-    int ccnt = cand >= 0 ? ldr(&lenv[cq]) : 0;
-    if (lane == 0) st(&s.A[x], SCANNED);
-    if (lane <= jx) bit_clear(s, lane, x);
-    // longer lists: the next 256 entries are loaded now as well
-    int yv[4] = {-1, -1, -1, -1};
-    if (cnt > 64) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        int e = 64 + 64 * k + lane;
-        if (e < cnt) yv[k] = entry(e0 + e);
-      }
+    int ce0 = 0, ccnt = 0;
+    if (cand >= 0) {
+      ce0 = ldr(&stv[cand]);
+      ccnt = ldr(&lenv[cand]);
+    }
+    // x leaves levels 0..jx (lanes at or below jx; one of them marks it scanned)
+    if (lane <= jx) {
+      atomicAnd((unsigned long long *)&s.bits[my_lv + xw], ~xbit);
+      st(&s.A[x], SCANNED);
     }
     int cy = -1;
     if (lane < ccnt) cy = entry(ce0 + lane);
-    int bl = -1, by = 0x7fffffff;  // this lane's highest raised level and smallest id there
-    if (old >= 0) scan_entry(s, x, y, old + 1, e0 + lane, bound, &bl, &by);
-    for (int base = 64; base < cnt; base += 256) {
-      if (base > 64) {
+    int bl = -1, by = 0;  // this lane's highest raised level and smallest id there
+    if (old >= 0) {
+      int nw = old + 1;
+      if (nw <= bound) bit_set(s, nw, y);
+      if (nw == bound) st(&s.B[y], x);          // contractible, first for y: parent
+      else if (nw > bound) mark_set(s, e0 + lane);  // contractible, extra edge
+      bl = nw < bound ? nw : bound;
+      by = y;
+    }
+    if (cnt > 64) {
+      // longer lists: four chunks' loads are issued together, then processed in order
+      for (int base = 64; base < cnt; base += 256) {
+        int yv[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           int e = base + 64 * k + lane;
           yv[k] = e < cnt ? entry(e0 + e) : -1;
         }
-      }
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        int e = base + 64 * k + lane;
-        if (e < cnt) {
-          int nw2 = atomicAdd(&s.A[yv[k]], 1) + 1;
-          if (nw2 > 0) scan_entry(s, x, yv[k], nw2, e0 + e, bound, &bl, &by);
+        for (int k = 0; k < 4; k++) {
+          int e = base + 64 * k + lane;
+          if (e < cnt) {
+            int nw2 = atomicAdd(&s.A[yv[k]], 1) + 1;
+            if (nw2 > 0) scan_entry(s, x, yv[k], nw2, e0 + e, bound, &bl, &by);
+          }
         }
       }
     }
@@ -708,8 +721,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     have = nx >= 0 && nx == cand;
     e0 = ce0;
     cnt = ccnt;
-    y0 = cy;
-    // (uniform: kept in scalar registers)
+    y = cy;
     x = __builtin_amdgcn_readfirstlane(nx);
     jx = __builtin_amdgcn_readfirstlane(jx);
   }
