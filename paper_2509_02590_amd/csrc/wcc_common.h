@@ -196,11 +196,13 @@ DEV unsigned long long wave_min_u64(unsigned long long v) {
   return v;
 }
 
-// Block-wide exclusive scan of one int per thread.  red must hold >= BLOCK/64 + 1 ints.
-// Returns the exclusive prefix; *total gets the block sum.  Contains barriers.
+// Block-wide reductions and scans for blocks of up to BLOCK threads (the block size of the
+// launch, a multiple of 64, is read at run time).  red must hold >= BLOCK/64 + 1 entries.
+// Block-wide exclusive scan of one int per thread.  Returns the exclusive prefix; *total
+// gets the block sum.  Contains barriers.
 template <int BLOCK>
 DEV int block_excl_scan(int v, int *red, int *total) {
-  constexpr int NW = BLOCK / 64;
+  const int NW = (int)(blockDim.x >> 6);
   int inc = wave_incl_sum(v);
   int w = threadIdx.x >> 6;
   if (__lane_id() == 63) red[w] = inc;
@@ -223,7 +225,7 @@ DEV int block_excl_scan(int v, int *red, int *total) {
 
 template <int BLOCK>
 DEV long long block_excl_scan64(long long v, long long *red, long long *total) {
-  constexpr int NW = BLOCK / 64;
+  const int NW = (int)(blockDim.x >> 6);
   long long inc = wave_incl_sum64(v);
   int w = threadIdx.x >> 6;
   if (__lane_id() == 63) red[w] = inc;
@@ -246,7 +248,7 @@ DEV long long block_excl_scan64(long long v, long long *red, long long *total) {
 
 template <int BLOCK>
 DEV unsigned long long block_min_u64(unsigned long long v, unsigned long long *red) {
-  constexpr int NW = BLOCK / 64;
+  const int NW = (int)(blockDim.x >> 6);
   v = wave_min_u64(v);
   int w = threadIdx.x >> 6;
   if (__lane_id() == 0) red[w] = v;

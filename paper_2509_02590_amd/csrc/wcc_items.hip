@@ -34,15 +34,19 @@
 
 namespace {
 
-constexpr int IB = 256;  // threads per item workgroup
-constexpr int NW = IB / 64;
+// threads per item workgroup: 256, or 512 for launches with one workgroup per CU (more
+// loads in flight in the item-wide passes); the loops stride by the launch's block size
+constexpr int IB_SMALL = 256;
+constexpr int IB_MAX = 512;
+constexpr int NW_MAX = IB_MAX / 64;
+DEV int ib() { return (int)blockDim.x; }
 constexpr int MAX_LEVEL = 62;
 constexpr int CH = 16;   // entries per thread per chunk in entry-parallel passes
 
 struct Sh {
-  int red[NW + 1];
-  long long red64[NW + 1];
-  unsigned long long redu[NW + 1];
+  int red[NW_MAX + 1];
+  long long red64[NW_MAX + 1];
+  unsigned long long redu[NW_MAX + 1];
   unsigned long long hsum;
   int vi[8];
 };
@@ -72,9 +76,9 @@ DEV void mark_set(const St &s, int e) {
 }
 DEV void mark_clear(const St &s, int total) {
   if (s.markbits)
-    for (int w = threadIdx.x; w < (total + 31) / 32; w += IB) st(&s.markbits[w], 0u);
+    for (int w = threadIdx.x; w < (total + 31) / 32; w += ib()) st(&s.markbits[w], 0u);
   else
-    for (int e = threadIdx.x; e < total; e += IB) st(&s.mark[e], 0);
+    for (int e = threadIdx.x; e < total; e += ib()) st(&s.mark[e], 0);
 }
 DEV int adj_at(const St &s, int e) { return s.adj16 ? (int)s.adj16[e] : s.adjg[e]; }
 
@@ -123,7 +127,7 @@ DEV void uf_unite(int32_t *P, int a, int b) {
 // and y = get(e).  Each thread takes CH consecutive entries.
 template <typename G, typename F>
 DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
-  for (int base = threadIdx.x * CH; base < total; base += IB * CH) {
+  for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
     int yv[CH];
 #pragma unroll
     for (int i = 0; i < CH; i++) yv[i] = base + i < total ? get(base + i) : 0;
@@ -153,7 +157,7 @@ DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
 // inside one skipped row is passed over without loading it.
 template <typename S, typename G, typename F>
 DEV void for_entries_skip(const int32_t *start, int n, int total, S skip, G get, F f) {
-  for (int base = threadIdx.x * CH; base < total; base += IB * CH) {
+  for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       int mid = (lo + hi + 1) >> 1;
@@ -194,7 +198,7 @@ DEV void for_entries_skip(const int32_t *start, int n, int total, S skip, G get,
 template <typename G, typename F>
 DEV void for_marked_entries(const St &s, const int32_t *start, int n, int total, G get, F f) {
   static_assert(CH == 16, "mark_chunk reads 16 entries");
-  for (int base = threadIdx.x * CH; base < total; base += IB * CH) {
+  for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
     uint32_t mk = mark_chunk(s, base, total);
     if (!mk) continue;
     int lo = 0, hi = n - 1;
@@ -353,13 +357,13 @@ DEV void err(const ItemArgs &A, int code) {
 DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     bool al = !use_deg || ld(&s.A[i]) >= kmin;
     st(&s.B[i], al ? i : -1);
     st(&s.E[i], 0);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     if (ld(&s.B[i]) < 0) continue;
     int r1 = row_end(s, i), found = 0;
     for (int e = ldr(&s.R[i]); e < r1 && found < 2; e++) {
@@ -372,7 +376,7 @@ DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   }
   __syncthreads();
   sub_mark(s, 16, &q);
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     if (ld(&s.B[i]) < 0) continue;
     int r = uf_find(s.B, i);
     st(&s.B[i], r);
@@ -381,14 +385,14 @@ DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   __syncthreads();
   sub_mark(s, 17, &q);
   unsigned long long best = ~0ull;
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     int c = ldr(&s.E[i]);
     if (c > 0) {
       unsigned long long v = ((unsigned long long)(uint32_t)(0x7fffffff - c) << 32) | (uint32_t)i;
       best = v < best ? v : best;
     }
   }
-  best = block_min_u64<IB>(best, sh.redu);
+  best = block_min_u64<IB_MAX>(best, sh.redu);
   const int cs = best == ~0ull ? -1 : (int)(best & 0xffffffffu);
   sub_mark(s, 18, &q);
   for_entries_skip(
@@ -400,13 +404,13 @@ DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   __syncthreads();
   sub_mark(s, 29, &q);
   int roots = 0;
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     if (ld(&s.B[i]) < 0) continue;
     int r = uf_find(s.B, i);
     roots += (r == i);
     st(&s.B[i], r);
   }
-  int nr = block_sum<IB>(roots, sh.red);  // includes barriers
+  int nr = block_sum<IB_MAX>(roots, sh.red);  // includes barriers
   sub_mark(s, 30, &q);
   return nr;
 }
@@ -421,26 +425,26 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   const Arena &nx = A.ar[(d.depth + 1) & 1];
   int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
-  for (int i = threadIdx.x; i < n; i += IB) st(&s.A[i], 0);
+  for (int i = threadIdx.x; i < n; i += ib()) st(&s.A[i], 0);
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     int L = ldr(&s.B[i]);
     if (L >= 0) atomicAdd(&s.A[L], 1);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     int L = ldr(&s.B[i]);
     if (L >= 0 && ldr(&s.A[L]) <= gate) st(&s.B[i], -1);
   }
   __syncthreads();
   // child starts: exclusive scan over representatives
   int carry = 0;
-  for (int base = 0; base < n; base += IB) {
+  for (int base = 0; base < n; base += ib()) {
     int i = base + threadIdx.x;
     int v = 0;
     if (i < n && ldr(&s.B[i]) == i) v = ldr(&s.A[i]);
     int tot;
-    int pre = block_excl_scan<IB>(v, sh.red, &tot);
+    int pre = block_excl_scan<IB_MAX>(v, sh.red, &tot);
     if (i < n) st(&s.D[i], carry + pre);
     carry += tot;
   }
@@ -468,7 +472,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   }
   __syncthreads();
   // D[L] now holds start + size; restore starts; clear new degrees and cursors
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     if (ldr(&s.B[i]) == i) st(&s.D[i], ldr(&s.D[i]) - ldr(&s.A[i]));
     if (i < K) {
       st(&s.C[i], 0);
@@ -484,18 +488,18 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   __syncthreads();
   // row offsets by new position (exclusive scan of C, in place)
   long long ecarry = 0;
-  for (int base = 0; base < K; base += IB) {
+  for (int base = 0; base < K; base += ib()) {
     int p = base + threadIdx.x;
     long long v = p < K ? (long long)ldr(&s.C[p]) : 0;
     long long tot;
-    long long pre = block_excl_scan64<IB>(v, sh.red64, &tot);
+    long long pre = block_excl_scan64<IB_MAX>(v, sh.red64, &tot);
     if (p < K) st(&s.C[p], (int)(ecarry + pre));
     ecarry += tot;
   }
   int M = (int)ecarry;
   __syncthreads();
   // vertex records of the children
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     int L = ldr(&s.B[i]);
     if (L < 0) continue;
     int np = ldr(&s.E[i]);
@@ -531,7 +535,7 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     c.flags = 0;
     return c;
   };
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     if (ldr(&s.B[i]) != i) continue;
     ItemDesc c = child(i);
     atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * c.n + 4LL * c.m));
@@ -555,7 +559,7 @@ DEV int item_peel(const St &s, int k, Sh &sh) {
   int n = s.n;
   if (threadIdx.x == 0) sh.vi[0] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     int dg = row_end(s, i) - ld(&s.R[i]);
     st(&s.A[i], dg);
     if (dg < k) st(&s.D[atomicAdd(&sh.vi[0], 1)], i);
@@ -568,7 +572,7 @@ DEV int item_peel(const St &s, int k, Sh &sh) {
     __syncthreads();
     if (threadIdx.x == 0) sh.vi[1] = 0;
     __syncthreads();
-    for (int f = threadIdx.x; f < cnt; f += IB) {
+    for (int f = threadIdx.x; f < cnt; f += ib()) {
       int u = ld(&cur[f]);
       int r0 = ld(&s.R[u]), r1 = row_end(s, u);
       for (int e = r0; e < r1; e++) {
@@ -735,12 +739,12 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   unsigned long long pt = s.pf ? wall_clock64() : 0;
   // Phase 0: minimum degree and its smallest vertex
   unsigned long long mv = ~0ull;
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     unsigned long long dg = (unsigned long long)(uint32_t)(row_end(s, i) - ldr(&s.R[i]));
     unsigned long long v = (dg << 32) | (uint32_t)i;
     mv = v < mv ? v : mv;
   }
-  mv = block_min_u64<IB>(mv, sh.redu);
+  mv = block_min_u64<IB_MAX>(mv, sh.redu);
   int delta = (int)(mv >> 32), dv = (int)(mv & 0xffffffffu);
   int bound = delta < cap ? delta : cap;
   int s_kind = delta <= cap ? 1 : 0;  // 0 empty, 1 singleton dv, 2 set in F
@@ -751,7 +755,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   }
   if (bound > 1) {
     // super-vertex ids C; round 1 scans the item's own rows (starts R, lengths D)
-    for (int i = threadIdx.x; i < n; i += IB) {
+    for (int i = threadIdx.x; i < n; i += ib()) {
       st(&s.C[i], i);
       st(&s.D[i], row_end(s, i) - ldr(&s.R[i]));
     }
@@ -761,14 +765,14 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       ph_mark(A, s, 3, &pt);
       // ---- round setup: keys, marks, bitmaps (levels 0..bound)
       int words = (bound + 1) * s.ls;
-      for (int w = threadIdx.x; w < words; w += IB) st(&s.bits[w], (uint64_t)0);
-      for (int x = threadIdx.x; x < n; x += IB) {
+      for (int w = threadIdx.x; w < words; w += ib()) st(&s.bits[w], (uint64_t)0);
+      for (int x = threadIdx.x; x < n; x += ib()) {
         st(&s.A[x], 0);
         st(&s.B[x], x);
       }
       mark_clear(s, total);
       __syncthreads();
-      for (int x = threadIdx.x; x < n; x += IB)
+      for (int x = threadIdx.x; x < n; x += ib())
         if (ldr(&s.C[x]) == x) bit_set(s, 0, x);
       __syncthreads();
       // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
@@ -796,7 +800,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       unsigned long long q = s.pf ? wall_clock64() : 0;
       // ---- contraction: parent forest, then unions of the extra marked entries; the new
       // id of a merged group is its smallest member (A serves as the group minimum)
-      for (int x = threadIdx.x; x < n; x += IB)
+      for (int x = threadIdx.x; x < n; x += ib())
         if (ld(&s.C[x]) == x) {
           st(&s.B[x], uf_find(s.B, x));
           st(&s.A[x], 0x7fffffff);
@@ -813,7 +817,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
         for_marked_entries(s, stv, n, total, [&](int e) { return ldr(&s.lists[e]); }, join);
       __syncthreads();
       sub_mark(s, 23, &q);
-      for (int x = threadIdx.x; x < n; x += IB)
+      for (int x = threadIdx.x; x < n; x += ib())
         if (ld(&s.C[x]) == x) {
           int r = uf_find(s.B, x);
           st(&s.B[x], r);
@@ -822,19 +826,19 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       __syncthreads();
       sub_mark(s, 24, &q);
       int reps = 0;
-      for (int v = threadIdx.x; v < n; v += IB) {
+      for (int v = threadIdx.x; v < n; v += ib()) {
         int c = ldr(&s.A[ldr(&s.B[ldr(&s.C[v])])]);
         st(&s.C[v], c);
         reps += (c == v);
       }
-      reps = block_sum<IB>(reps, sh.red);
+      reps = block_sum<IB_MAX>(reps, sh.red);
       sub_mark(s, 25, &q);
       ph_mark(A, s, 5, &pt);
       if (reps <= 1) break;
       first = false;
       // ---- crossing lists of the contracted graph (D = weighted degree, E = start)
       // (the contraction marks are dead now: they flag the crossing entries instead)
-      for (int x = threadIdx.x; x < n; x += IB) st(&s.D[x], 0);
+      for (int x = threadIdx.x; x < n; x += ib()) st(&s.D[x], 0);
       mark_clear(s, s.m);
       __syncthreads();
       for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int e, int u) {
@@ -847,11 +851,11 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       __syncthreads();
       sub_mark(s, 26, &q);
       int carry = 0;
-      for (int base = 0; base < n; base += IB) {
+      for (int base = 0; base < n; base += ib()) {
         int x = base + threadIdx.x;
         int v = x < n ? ld(&s.D[x]) : 0;
         int tot;
-        int pre = block_excl_scan<IB>(v, sh.red, &tot);
+        int pre = block_excl_scan<IB_MAX>(v, sh.red, &tot);
         if (x < n) {
           st(&s.E[x], carry + pre);
           st(&s.A[x], carry + pre);  // fill cursor
@@ -872,17 +876,17 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       ph_mark(A, s, 6, &pt);
       // ---- degree check: smallest id of minimum weighted degree, strict improvement
       unsigned long long dm = ~0ull;
-      for (int x = threadIdx.x; x < n; x += IB)
+      for (int x = threadIdx.x; x < n; x += ib())
         if (ldr(&s.C[x]) == x) {
           unsigned long long v = ((unsigned long long)(uint32_t)ldr(&s.D[x]) << 32) | (uint32_t)x;
           dm = v < dm ? v : dm;
         }
-      dm = block_min_u64<IB>(dm, sh.redu);
+      dm = block_min_u64<IB_MAX>(dm, sh.redu);
       int dmin = (int)(dm >> 32), xmin = (int)(dm & 0xffffffffu);
       if (dmin < bound) {
         bound = dmin;
         s_kind = 2;
-        for (int v = threadIdx.x; v < n; v += IB) st(&s.F[v], (int32_t)(ldr(&s.C[v]) == xmin));
+        for (int v = threadIdx.x; v < n; v += ib()) st(&s.F[v], (int32_t)(ldr(&s.C[v]) == xmin));
         __syncthreads();
         if (bound <= 1) break;
       }
@@ -890,7 +894,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
     }
   }
   if (s_kind != 2)
-    for (int v = threadIdx.x; v < n; v += IB) st(&s.F[v], (int32_t)(s_kind == 1 && v == dv));
+    for (int v = threadIdx.x; v < n; v += ib()) st(&s.F[v], (int32_t)(s_kind == 1 && v == dv));
   __syncthreads();
   *steps_out += steps;
   *rounds_out += rounds;
@@ -1004,15 +1008,15 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   // every item reads its rows at least once: vtx, rs, rd per vertex and one index per entry
   if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * n + 4LL * d.m));
   // row starts relative to eb, and the LDS copy of the adjacency when it fits
-  for (int i = threadIdx.x; i < n; i += IB) st(&s.R[i], (int32_t)(ar.rs[d.b + i] - d.eb));
+  for (int i = threadIdx.x; i < n; i += ib()) st(&s.R[i], (int32_t)(ar.rs[d.b + i] - d.eb));
   if (s.adj16)
-    for (int e = threadIdx.x; e < s.m; e += IB) s.adj16[e] = (uint16_t)s.adjg[e];
+    for (int e = threadIdx.x; e < s.m; e += ib()) s.adj16[e] = (uint16_t)s.adjg[e];
   __syncthreads();
 
   if (A.ccr_out) {
     // components of the cluster's induced subgraph (Alg. 1), labelled by smallest member
     item_cc(s, false, 0, sh);
-    for (int i = threadIdx.x; i < n; i += IB) A.ccr_out[ar.vtx[d.b + i]] = ar.vtx[d.b + ld(&s.B[i])];
+    for (int i = threadIdx.x; i < n; i += ib()) A.ccr_out[ar.vtx[d.b + i]] = ar.vtx[d.b + ld(&s.B[i])];
     __syncthreads();
     return;
   }
@@ -1022,17 +1026,17 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     int lam;
     if (n < 2) {
       lam = 0;
-      for (int i = threadIdx.x; i < n; i += IB) st(&s.F[i], 0);
+      for (int i = threadIdx.x; i < n; i += ib()) st(&s.F[i], 0);
       __syncthreads();
     } else if (nc > 1) {
       lam = 0;
-      for (int i = threadIdx.x; i < n; i += IB) st(&s.F[i], (int32_t)(ld(&s.B[i]) == 0));
+      for (int i = threadIdx.x; i < n; i += ib()) st(&s.F[i], (int32_t)(ld(&s.B[i]) == 0));
       __syncthreads();
     } else {
       lam = item_mincut(A, s, d, cap, sh, &steps, &rounds);
     }
     int64_t p0 = A.split_pos[set];
-    for (int i = threadIdx.x; i < n; i += IB) A.split_side[p0 + i] = (uint8_t)ld(&s.F[i]);
+    for (int i = threadIdx.x; i < n; i += ib()) A.split_side[p0 + i] = (uint8_t)ld(&s.F[i]);
     if (threadIdx.x == 0) {
       A.split_lambda[set] = lam;
       atomicAdd(&A.cnt[CNT_STEPS], (unsigned long long)steps);
@@ -1075,13 +1079,13 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   unsigned long long hs = 0;
   if (threadIdx.x == 0) sh.hsum = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += IB)
+  for (int i = threadIdx.x; i < n; i += ib())
     if (ld(&s.F[i])) {
       ss++;
       hs += vhash(ar.vtx[d.b + i]);
     }
   if (hs) atomicAdd(&sh.hsum, hs);
-  ss = block_sum<IB>(ss, sh.red);
+  ss = block_sum<IB_MAX>(ss, sh.red);
   if (threadIdx.x == 0) {
     atomicAdd(&A.cnt[CNT_MINCUTS], 1ull);
     atomicAdd(&A.cnt[CNT_STEPS], (unsigned long long)steps);
@@ -1103,7 +1107,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   }
   if (lam >= k) {  // cut > f(n): save the set under its smallest global id
     int key = ar.vtx[d.b];
-    for (int i = threadIdx.x; i < n; i += IB) A.acc[ar.vtx[d.b + i]] = key;
+    for (int i = threadIdx.x; i < n; i += ib()) A.acc[ar.vtx[d.b + i]] = key;
     if (threadIdx.x == 0) {
       atomicAdd(&A.cnt[CNT_ACCEPTED], 1ull);
       atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(4LL * n));
@@ -1113,13 +1117,13 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   }
   // split along the cut: label each side by its smallest member
   unsigned long long mS = ~0ull, mC = ~0ull;
-  for (int i = threadIdx.x; i < n; i += IB) {
+  for (int i = threadIdx.x; i < n; i += ib()) {
     if (ld(&s.F[i])) mS = (unsigned long long)i < mS ? (unsigned long long)i : mS;
     else mC = (unsigned long long)i < mC ? (unsigned long long)i : mC;
   }
-  mS = block_min_u64<IB>(mS, sh.redu);
-  mC = block_min_u64<IB>(mC, sh.redu);
-  for (int i = threadIdx.x; i < n; i += IB) st(&s.B[i], ld(&s.F[i]) ? (int)mS : (int)mC);
+  mS = block_min_u64<IB_MAX>(mS, sh.redu);
+  mC = block_min_u64<IB_MAX>(mC, sh.redu);
+  for (int i = threadIdx.x; i < n; i += ib()) st(&s.B[i], ld(&s.F[i]) ? (int)mS : (int)mC);
   __syncthreads();
   ph_mark(A, s, 8, &pt);
   item_rebuild(A, s, d, A.s_post, sh);
@@ -1139,7 +1143,7 @@ DEV void process_item(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int i
   else process_item_t<true, false>(A, d, dyn, item_index, sh);
 }
 
-__global__ void __launch_bounds__(IB) k_items(ItemArgs A) {
+__global__ void __launch_bounds__(IB_MAX) k_items(ItemArgs A) {
   extern __shared__ uint64_t dyn[];
   __shared__ Sh sh;
   __shared__ int cur;
@@ -1257,7 +1261,7 @@ __global__ void k_relabel(const int32_t *acc, const int32_t *rank, int64_t N, in
 
 }  // namespace
 
-int items_block() { return IB; }
+int items_block() { return IB_SMALL; }
 
 // LDS words a workgroup needs to keep an item's scan arrays of n vertices (cut cap `cap`)
 // in LDS (the 16-bit adjacency copy is optional on top of this)
@@ -1289,7 +1293,8 @@ int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
     HIP_TRY(attr_rc);
     if (lds_bytes > 159 * 1024) return WCC_EINVAL;
   }
-  hipLaunchKernelGGL(k_items, dim3(grid), dim3(IB), lds_bytes, s, A);
+  int block = lds_bytes > 65536 ? IB_MAX : IB_SMALL;
+  hipLaunchKernelGGL(k_items, dim3(grid), dim3(block), lds_bytes, s, A);
   HIP_TRY(hipGetLastError());
   return WCC_OK;
 }
