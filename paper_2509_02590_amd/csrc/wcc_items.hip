@@ -626,6 +626,11 @@ DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *bl
 // empty.  The successor's list start, length and first 64 entries are loaded while the
 // current step runs, so a step that continues with the successor issues its first key
 // increments at once; only the bitmap word of x is read before them.
+// Index of entry i of a list [e0, e0 + cnt), clamped into the list (entry 0 of all lists
+// when it is empty), so that list loads need no per-lane branch: lanes past the end load
+// a valid entry and ignore it.  (During a scan every list array holds at least one entry.)
+DEV int clamp_idx(int e0, int i, int cnt) { return cnt > 0 ? e0 + (i < cnt ? i : cnt - 1) : 0; }
+
 template <bool L16>
 DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
                    const uint16_t *list16, int bound) {
@@ -659,12 +664,16 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     if (!have) {
       e0 = ldr(&stv[x]);
       cnt = ldr(&lenv[x]);
-      y = lane < cnt ? entry(e0 + lane) : -1;
+      y = entry(clamp_idx(e0, lane, cnt));
     }
     // first 64 increments; their results are used only after the successor's loads
     // below have been issued
     int old = -1;
     if (lane < cnt) old = atomicAdd(&s.A[y], 1);
+    // y is complete here; re-defining it in an empty asm statement keeps the compiler from
+    // waiting again where y is used below, which would also wait for the prefetch issued
+    // in between
+    asm volatile("" : "+v"(y));
     uint64_t rest = w0 & ~xbit;
     int cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
     int ce0 = 0, ccnt = 0;
@@ -677,8 +686,14 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       atomicAnd((unsigned long long *)&s.bits[my_lv + xw], ~xbit);
       st(&s.A[x], SCANNED);
     }
-    int cy = -1;
-    if (lane < ccnt) cy = entry(ce0 + lane);
+    // longer lists: the next 256 entries are loaded before the prefetch below, so that
+    // waiting for them does not wait for it
+    int yv[4];
+    if (cnt > 64) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) yv[k] = entry(clamp_idx(e0, 64 + 64 * k + lane, cnt));
+    }
+    int cy = entry(clamp_idx(ce0, lane, ccnt));
     int bl = -1, by = 0;  // this lane's highest raised level and smallest id there
     if (old >= 0) {
       int nw = old + 1;
@@ -689,22 +704,18 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       by = y;
     }
     if (cnt > 64) {
-      // longer lists: four chunks' loads are issued together, then processed in order
+      // four chunks at a time: loads, then the increments, then their effects
       for (int base = 64; base < cnt; base += 256) {
-        int yv[4];
+        if (base > 64) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-          int e = base + 64 * k + lane;
-          yv[k] = e < cnt ? entry(e0 + e) : -1;
+          for (int k = 0; k < 4; k++) yv[k] = entry(clamp_idx(e0, base + 64 * k + lane, cnt));
         }
+        int ov[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-          int e = base + 64 * k + lane;
-          if (e < cnt) {
-            int nw2 = atomicAdd(&s.A[yv[k]], 1) + 1;
-            if (nw2 > 0) scan_entry(s, x, yv[k], nw2, e0 + e, bound, &bl, &by);
-          }
-        }
+        for (int k = 0; k < 4; k++) ov[k] = base + 64 * k + lane < cnt ? atomicAdd(&s.A[yv[k]], 1) : -1;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (ov[k] >= 0) scan_entry(s, x, yv[k], ov[k] + 1, e0 + base + 64 * k + lane, bound, &bl, &by);
       }
     }
     // only keys raised to jx or above can decide the next vertex; when there are any, one
