@@ -707,13 +707,14 @@ int collect_counts(Workspace &w, wcc_stats *st, int64_t *nrec, bool prof, hipStr
   if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
   if (prof) {
     static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
-                                  "lists", "degree", "record", "split-rebuild", "steps", "", "rounds"};
+                                  "lists", "degree", "record", "split-rebuild", "steps", "certified", "rounds"};
     fprintf(stderr, "[wcc phase ms, summed over workgroups]");
     for (int i = 0; i < 13; i++)
       if (names[i][0])
         fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
-    fprintf(stderr, "\n[wcc cc ms] sample=%.2f compress=%.2f pick=%.2f\n", hc[CNT_PH + 16] / 1e5,
-            hc[CNT_PH + 17] / 1e5, hc[CNT_PH + 18] / 1e5);
+    fprintf(stderr, "\n[wcc cc ms] sample=%.2f compress=%.2f pick=%.2f; certificate: sample=%.2f compress=%.2f pass=%.2f\n",
+            hc[CNT_PH + 16] / 1e5, hc[CNT_PH + 17] / 1e5, hc[CNT_PH + 18] / 1e5, hc[CNT_PH + 19] / 1e5,
+            hc[CNT_PH + 20] / 1e5, hc[CNT_PH + 21] / 1e5);
     fprintf(stderr, "[wcc sub-phases ms] forest=%.2f unions=%.2f finds=%.2f relabel=%.2f lists-count=%.2f "
             "lists-scan=%.2f lists-fill=%.2f cc-unite=%.2f cc-roots=%.2f rebuild-head=%.2f\n",
             hc[CNT_PH + 22] / 1e5, hc[CNT_PH + 23] / 1e5, hc[CNT_PH + 24] / 1e5, hc[CNT_PH + 25] / 1e5,

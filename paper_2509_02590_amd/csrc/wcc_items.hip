@@ -74,6 +74,9 @@ DEV void mark_set(const St &s, int e) {
   if (s.markbits) atomicOr(&s.markbits[e >> 5], 1u << (e & 31));
   else st(&s.mark[e], 1);
 }
+DEV bool mark_get(const St &s, int e) {
+  return s.markbits ? ((ld(&s.markbits[e >> 5]) >> (e & 31)) & 1u) : ld(&s.mark[e]) != 0;
+}
 DEV void mark_clear(const St &s, int total) {
   if (s.markbits)
     for (int w = threadIdx.x; w < (total + 31) / 32; w += ib()) st(&s.markbits[w], 0u);
@@ -119,6 +122,21 @@ DEV void uf_unite(int32_t *P, int a, int b) {
       b = t;
     }
     if (atomicCAS(&P[a], a, b) == a) return;
+  }
+}
+
+// uf_unite that reports whether this call joined two trees (hooked a root).
+DEV bool uf_link(int32_t *P, int a, int b) {
+  for (;;) {
+    a = uf_find(P, a);
+    b = uf_find(P, b);
+    if (a == b) return false;
+    if (a < b) {
+      int t = a;
+      a = b;
+      b = t;
+    }
+    if (atomicCAS(&P[a], a, b) == a) return true;
   }
 }
 
@@ -743,6 +761,54 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
   return steps;
 }
 
+// Certificate of lambda >= t: t edge-disjoint spanning trees (every cut crosses each of
+// them).  Built greedily, one spanning forest per pass over the edges not used by earlier
+// forests; an edge belongs to a forest when its union-find link joined two trees, so a
+// forest spans the item exactly when n - 1 links succeeded.  Each pass first links every
+// vertex with up to two sampled unused larger neighbours and flattens the trees, after
+// which most edges join one tree and stop at a single comparison.  Uses B (union-find) and the
+// entry marks (used edges); returns false as soon as a forest does not span (the greedy
+// choice can fail even when lambda >= t: the caller then runs the scans).
+DEV bool forest_certificate(const St &s, int t, Sh &sh) {
+  const int n = s.n;
+  unsigned long long q = s.pf ? wall_clock64() : 0;
+  mark_clear(s, s.m);
+  for (int f = 0; f < t; f++) {
+    for (int x = threadIdx.x; x < n; x += ib()) st(&s.B[x], x);
+    __syncthreads();
+    int links = 0;
+    for (int x = threadIdx.x; x < n; x += ib()) {
+      // two entries of x's row, at a different place for every forest
+      int r0 = ldr(&s.R[x]), dg = row_end(s, x) - r0;
+      int e1 = r0 + (2 * f) % dg, e2 = r0 + (2 * f + 1) % dg;
+      int y1 = adj_at(s, e1), y2 = adj_at(s, e2);
+      if (y1 > x && !mark_get(s, e1) && uf_link(s.B, x, y1)) {
+        mark_set(s, e1);
+        links++;
+      }
+      if (e2 != e1 && y2 > x && !mark_get(s, e2) && uf_link(s.B, x, y2)) {
+        mark_set(s, e2);
+        links++;
+      }
+    }
+    __syncthreads();
+    sub_mark(s, 19, &q);
+    for (int x = threadIdx.x; x < n; x += ib()) st(&s.B[x], uf_find(s.B, x));
+    __syncthreads();
+    sub_mark(s, 20, &q);
+    for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
+      if (y > x && ld(&s.B[x]) != ld(&s.B[y]) && !mark_get(s, e) && uf_link(s.B, x, y)) {
+        mark_set(s, e);
+        links++;
+      }
+    });
+    links = block_sum<IB_MAX>(links, sh.red);  // includes barriers
+    sub_mark(s, 21, &q);
+    if (links < n - 1) return false;
+  }
+  return true;
+}
+
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
 DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, Sh &sh,
                     long long *steps_out, long long *rounds_out) {
@@ -764,6 +830,13 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
     err(A, WCC_EUNSUPPORTED);
     bound = 1;  // give up on this item; the error is reported
   }
+  // lambda >= bound: no super-vertex degree can fall below the bound, so the rounds would
+  // end with (bound, the Phase-0 set); a certificate of it gives the same result at once
+  if (bound > 1 && forest_certificate(s, bound, sh)) {
+    if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
+    bound = -bound;  // (certified; restored below)
+  }
+  ph_mark(A, s, 3, &pt);
   if (bound > 1) {
     // super-vertex ids C; round 1 scans the item's own rows (starts R, lengths D)
     for (int i = threadIdx.x; i < n; i += ib()) {
@@ -904,6 +977,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
       ph_mark(A, s, 7, &pt);
     }
   }
+  if (bound < 0) bound = -bound;
   if (s_kind != 2)
     for (int v = threadIdx.x; v < n; v += ib()) st(&s.F[v], (int32_t)(s_kind == 1 && v == dv));
   __syncthreads();
