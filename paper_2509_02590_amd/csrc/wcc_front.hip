@@ -169,19 +169,21 @@ __global__ void k_cluster_tables(const uint32_t *keys, const uint32_t *vals, con
   vtx0[p] = (int32_t)v;
 }
 
-__global__ void k_cluster_locals(const int32_t *vtx0, const int32_t *cidv, const int64_t *cl_start,
-                                 const FrontCounts *fc, int32_t *locv) {
+// posv[v] = v's cluster-major position (its local id plus its cluster's start), -1 for an
+// unassigned vertex (filled beforehand).  u is in cluster c exactly when posv[u] lies in
+// [cl_start[c], cl_start[c+1]), so the compaction gathers one word per entry.
+__global__ void k_cluster_pos(const int32_t *vtx0, const FrontCounts *fc, int32_t *posv) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= fc->na) return;
-  int32_t v = vtx0[p];
-  locv[v] = (int32_t)(p - cl_start[cidv[v]]);
+  posv[vtx0[p]] = (int32_t)p;
 }
 
 // ---------------------------------------------------------------- compaction
 // deg_in[v] = number of neighbours of v inside v's cluster
 template <typename OT>
 __global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t *idx, int64_t N,
-                                                    int64_t nnz, const int32_t *cidv, int32_t *deg_in) {
+                                                    int64_t nnz, const int32_t *cidv, const int32_t *posv,
+                                                    const int64_t *cl_start, int32_t *deg_in) {
   __shared__ int64_t sh_r[2];
   __shared__ int64_t cache[FROWS];
   __shared__ int cnt[FROWS];
@@ -198,8 +200,8 @@ __global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t
     int64_t v = r0 + r;
     int32_t cv = cidv[v];
     if (cv < 0) continue;
-    int32_t u = idx[e];
-    if (cidv[u] == cv) {
+    int32_t pu = posv[idx[e]];
+    if (pu >= cl_start[cv] && pu < cl_start[cv + 1]) {
       if (cached) atomicAdd(&cnt[r], 1);
       else atomicAdd(&deg_in[v], 1);
     }
@@ -225,7 +227,7 @@ __global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t
 template <typename OT>
 __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t *idx, int64_t N,
                                                    int64_t nnz, const int32_t *cidv,
-                                                   const int32_t *locv, const int64_t *cl_start,
+                                                   const int32_t *posv, const int64_t *cl_start,
                                                    const int64_t *rs0, int32_t *cursor,
                                                    int32_t *adj0) {
   __shared__ int64_t sh_r[2];
@@ -241,11 +243,11 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
       int64_t v = row_of(off, r0, r1, e);
       int32_t cv = cidv[v];
       if (cv < 0) continue;
-      int32_t u = idx[e];
-      if (cidv[u] != cv) continue;
-      int64_t pv = cl_start[cv] + locv[v];
+      int64_t lo = cl_start[cv];
+      int32_t pu = posv[idx[e]];
+      if (pu < lo || pu >= cl_start[cv + 1]) continue;
       int32_t slot = atomicAdd(&cursor[v], 1);
-      adj0[rs0[pv] + slot] = locv[u];
+      adj0[rs0[posv[v]] + slot] = (int32_t)(pu - lo);
     }
     return;
   }
@@ -262,9 +264,10 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
     row[i] = r;
     int32_t cv = cidv[r0 + r];
     if (cv < 0) continue;
-    int32_t u = idx[e];
-    if (cidv[u] != cv) continue;
-    val[i] = locv[u];
+    int64_t lo = cl_start[cv];
+    int32_t pu = posv[idx[e]];
+    if (pu < lo || pu >= cl_start[cv + 1]) continue;
+    val[i] = (int32_t)(pu - lo);
     slot[i] = atomicAdd(&cnt[r], 1);
   }
   __syncthreads();
@@ -273,8 +276,7 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
     int c = cnt[r];
     if (c == 0) continue;
     int64_t v = r0 + r;
-    int64_t pv = cl_start[cidv[v]] + locv[v];
-    cache[r] = rs0[pv] + atomicAdd(&cursor[v], c);
+    cache[r] = rs0[posv[v]] + atomicAdd(&cursor[v], c);
   }
   __syncthreads();
 #pragma unroll
@@ -357,6 +359,7 @@ int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_
   if ((rc = prim_fill32(fc, 0u, (int64_t)(sizeof(FrontCounts) / 4), s))) return rc;
   if ((rc = prim_fill32(&fc->maxid, 0xffffffffu, 1, s))) return rc;
   if ((rc = prim_fill32(f.cidv, 0xffffffffu, N, s))) return rc;
+  if ((rc = prim_fill32(f.posv, 0xffffffffu, N, s))) return rc;  // cluster-major positions
   if ((rc = prim_fill32(cl_start, 0u, 2, s))) return rc;
   if (N > 0) hipLaunchKernelGGL(k_member_stats, dim3(nblk(N, 1024)), dim3(1024), 0, s, f.mem, N, fc);
   hipLaunchKernelGGL(k_sort_init, dim3(nblk(N, 256)), dim3(256), 0, s, f.mem, N, (const FrontCounts *)fc,
@@ -373,8 +376,8 @@ int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_
   if (rc) return rc;
   hipLaunchKernelGGL(k_cluster_tables, dim3(nblk(N, 256)), dim3(256), 0, s, keys, vals, f.flag, f.flag_scan, N,
                      (const FrontCounts *)fc, cl_start, cl_ids, f.cidv, vtx0);
-  hipLaunchKernelGGL(k_cluster_locals, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, f.cidv, cl_start,
-                     (const FrontCounts *)fc, f.locv);
+  hipLaunchKernelGGL(k_cluster_pos, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, (const FrontCounts *)fc,
+                     f.posv);
   HIP_TRY(hipGetLastError());
   // counting pass: intra degree per vertex, then row starts by position
   if ((rc = prim_fill32(f.deg_in, 0u, N, s))) return rc;
@@ -382,10 +385,10 @@ int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
       hipLaunchKernelGGL(k_count_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.deg_in);
+                         f.N, f.nnz, f.cidv, f.posv, cl_start, f.deg_in);
     else
       hipLaunchKernelGGL(k_count_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.deg_in);
+                         f.N, f.nnz, f.cidv, f.posv, cl_start, f.deg_in);
   }
   hipLaunchKernelGGL(k_gather_deg, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, f.deg_in, N,
                      (const FrontCounts *)fc, rd0, rs0);
@@ -399,10 +402,10 @@ int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
       hipLaunchKernelGGL(k_fill_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.locv, cl_start, rs0, f.cursor, adj0);
+                         f.N, f.nnz, f.cidv, f.posv, cl_start, rs0, f.cursor, adj0);
     else
       hipLaunchKernelGGL(k_fill_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.locv, cl_start, rs0, f.cursor, adj0);
+                         f.N, f.nnz, f.cidv, f.posv, cl_start, rs0, f.cursor, adj0);
   }
   if (items)
     hipLaunchKernelGGL(k_make_items, dim3(nblk(N, 256)), dim3(256), 0, s, cl_start, (const int32_t *)cl_ids, N,

@@ -12,7 +12,7 @@ struct FrontBufs {
   int64_t N, nnz;
   uint32_t *keys, *vals, *keys2, *vals2;   // N each
   int32_t *flag, *flag_scan;               // N each
-  int32_t *cidv, *locv, *deg_in, *cursor;  // N each
+  int32_t *cidv, *posv, *deg_in, *cursor;  // N each (posv: cluster-major position)
   void *tmp;
   size_t tmp_bytes;
   unsigned long long *dcnt;                // >= 8 device counters
