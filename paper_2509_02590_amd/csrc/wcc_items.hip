@@ -809,6 +809,71 @@ DEV bool forest_certificate(const St &s, int t, Sh &sh) {
   return true;
 }
 
+// The same certificate for t <= 4 with all forests built in one pass: forest f keeps its
+// union-find in B, A, D or E (free before the rounds), every vertex first links up to two
+// sampled edges per forest, and then every unused edge joins the first forest whose trees
+// it connects.  One pass over the edges instead of t.
+DEV bool forest_certificate4(const St &s, int t, Sh &sh) {
+  const int n = s.n;
+  auto P = [&](int f) -> int32_t * { return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : s.E; };
+  unsigned long long q = s.pf ? wall_clock64() : 0;
+  mark_clear(s, s.m);
+  for (int x = threadIdx.x; x < n; x += ib()) {
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+      if (f < t) st(&P(f)[x], x);
+  }
+  __syncthreads();
+  int links[4] = {0, 0, 0, 0};
+  for (int x = threadIdx.x; x < n; x += ib()) {
+    int r0 = ldr(&s.R[x]), dg = row_end(s, x) - r0;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      if (f >= t) break;
+      // two entries of x's row, at a different place for every forest
+      int e1 = r0 + (2 * f) % dg, e2 = r0 + (2 * f + 1) % dg;
+      int y1 = adj_at(s, e1), y2 = adj_at(s, e2);
+      if (y1 > x && !mark_get(s, e1) && uf_link(P(f), x, y1)) {
+        mark_set(s, e1);
+        links[f]++;
+      }
+      if (e2 != e1 && y2 > x && !mark_get(s, e2) && uf_link(P(f), x, y2)) {
+        mark_set(s, e2);
+        links[f]++;
+      }
+    }
+  }
+  __syncthreads();
+  sub_mark(s, 19, &q);
+  for (int x = threadIdx.x; x < n; x += ib()) {
+#pragma unroll
+    for (int f = 0; f < 4; f++)
+      if (f < t) st(&P(f)[x], uf_find(P(f), x));
+  }
+  __syncthreads();
+  sub_mark(s, 20, &q);
+  for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
+    if (y <= x || mark_get(s, e)) return;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+      if (f >= t) break;
+      int32_t *Pf = P(f);
+      if (ld(&Pf[x]) != ld(&Pf[y]) && uf_link(Pf, x, y)) {
+        links[f]++;
+        break;
+      }
+    }
+  });
+  bool ok = true;
+#pragma unroll
+  for (int f = 0; f < 4; f++) {
+    int l = block_sum<IB_MAX>(links[f], sh.red);  // includes barriers
+    if (f < t && l < n - 1) ok = false;
+  }
+  sub_mark(s, 21, &q);
+  return ok;
+}
+
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
 DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, Sh &sh,
                     long long *steps_out, long long *rounds_out) {
@@ -832,7 +897,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   }
   // lambda >= bound: no super-vertex degree can fall below the bound, so the rounds would
   // end with (bound, the Phase-0 set); a certificate of it gives the same result at once
-  if (bound > 1 && forest_certificate(s, bound, sh)) {
+  if (bound > 1 && (bound <= 4 ? forest_certificate4(s, bound, sh) : forest_certificate(s, bound, sh))) {
     if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
     bound = -bound;  // (certified; restored below)
   }
