@@ -897,7 +897,9 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   }
   // lambda >= bound: no super-vertex degree can fall below the bound, so the rounds would
   // end with (bound, the Phase-0 set); a certificate of it gives the same result at once
-  if (bound > 1 && (bound <= 4 ? forest_certificate4(s, bound, sh) : forest_certificate(s, bound, sh))) {
+  // (bound spanning trees need bound * (n - 1) edges: sparser items skip the attempt)
+  if (bound > 1 && (long long)s.m / 2 >= (long long)bound * (n - 1) &&
+      (bound <= 4 ? forest_certificate4(s, bound, sh) : forest_certificate(s, bound, sh))) {
     if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
     bound = -bound;  // (certified; restored below)
   }
