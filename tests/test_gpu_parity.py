@@ -112,6 +112,49 @@ def test_mincut_split_single_and_disconnected():
     assert lam == 4 and side.cpu().numpy().tolist() == [1, 0, 0, 0, 0]
 
 
+def _cert_graph(rng):
+    """Clusters that reach the spanning-forest certificate in every way: dense ones it
+    certifies, sparse ones with fewer edges than the certificate needs, two dense halves
+    joined by fewer bridges than k (the certificate must fail and the scan split them),
+    and complete bipartite ones whose cut equals their minimum degree."""
+    parts, base = [], 0
+    def add(n, edges):
+        nonlocal base
+        parts.append((base, n, [(a + base, b + base) for a, b in edges]))
+        base += n
+    for n in (12, 20, 33, 60):
+        add(n, complete(n))
+    for n in (40, 120):
+        ring = cycle(n) + [(i, (i + n // 2) % n) for i in range(0, n, 7)]
+        add(n, sorted({(min(a, b), max(a, b)) for a, b in ring if a != b}))
+    for h, b in ((15, 1), (30, 2), (60, 2)):
+        e = complete(h) + [(a + h, c + h) for a, c in complete(h)]
+        e += [(int(rng.integers(0, h)), int(rng.integers(h, 2 * h))) for _ in range(b)]
+        add(2 * h, sorted(set(e)))
+    for a, b in ((6, 9), (12, 14)):
+        add(a + b, [(i, a + j) for i in range(a) for j in range(b)])
+    memb = np.concatenate([np.full(n, i, np.int32) for i, (_, n, _) in enumerate(parts)])
+    edges = [e for _, _, es in parts for e in es]
+    # a few edges between clusters
+    for _ in range(40):
+        u, v = rng.integers(0, base, 2)
+        if memb[u] != memb[v]:
+            edges.append((int(min(u, v)), int(max(u, v))))
+    off, adj = csr_from_edges(base, sorted(set(edges)))
+    return off, adj, memb
+
+
+@pytest.mark.parametrize("mode", ["kcore", "paper"])
+def test_certificate_and_scan_paths(mode):
+    """Items ended by the certificate, items too sparse for it, and items it cannot
+    certify (lambda below the bound) all give the oracle's membership and records."""
+    rng = np.random.default_rng(303 if mode == "kcore" else 304)
+    off, adj, memb = _cert_graph(rng)
+    for crit in ("log10", "log2"):
+        st = _compare(off, adj, memb, mode=mode, criterion=crit)
+        assert st.mincuts > 0
+
+
 # ------------------------------------------------------------------ whole WCC
 @pytest.mark.parametrize("mode", ["kcore", "paper"])
 def test_wcc_tiny_workload(mode):
