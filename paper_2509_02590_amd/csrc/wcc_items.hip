@@ -11,23 +11,24 @@
 //
 // Placement.  The arrays the scan touches every step (keys A, union-find B, list lengths
 // D and starts E, row starts R and the level bitmaps) live in LDS when they fit the
-// launch's LDS budget, otherwise in global scratch; the item's own adjacency is also
-// copied to LDS as 16-bit ids when it fits too.  Super-vertex ids C, the cut side F and
-// the per-entry contraction marks always live in global scratch.  Items of one launch
-// are disjoint, so position- and entry-indexed scratch slices never overlap.
+// launch's LDS budget, otherwise in global scratch; the contraction marks, the
+// super-vertex ids C and the item's own adjacency (as 16-bit ids) join them in LDS when
+// room is left.  The cut side F and the crossing lists of later rounds live in global
+// scratch.  Items of one launch are disjoint, so position- and entry-indexed scratch
+// slices never overlap.
 //
 // The maximum-adjacency scan is run by one wavefront.  For every key level j in 0..bound
-// a hierarchical bitmap holds the unscanned super-vertices whose key is >= j (level 0 =
-// all unscanned); the next vertex is the smallest id of the highest non-empty level.  A
-// key increment sets exactly one bit, so concurrent increments commute; contractible
-// edges are only marked during the scan (a store nobody waits for) and merged with a
-// union-find pass afterwards.  When the neighbour lists are in global memory the list
-// of the likely next vertex is prefetched into registers while the current one is
-// processed.
+// a bitmap holds the unscanned super-vertices whose key is >= j (level 0 = all
+// unscanned); the next vertex is the smallest id of the highest non-empty level.  A key
+// increment sets exactly one bit, so concurrent increments commute; contractible edges
+// are only marked during the scan (a store nobody waits for) and merged with a
+// union-find pass afterwards.  The list of the likely next vertex is loaded into
+// registers while the current one is processed.  Before the scans, a certificate of
+// lambda >= bound (edge-disjoint spanning forests) ends most items whose cut reaches the
+// bound.
 //
 // Passes over all edges of an item are entry-parallel: each thread takes 16 consecutive
-// entries (coalesced loads) and finds their owners by a binary search in the LDS copy
-// of the row starts.
+// entries and finds their owners by a binary search in the LDS copy of the row starts.
 #include <mutex>
 
 #include "wcc_internal.h"
