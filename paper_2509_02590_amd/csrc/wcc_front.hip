@@ -171,7 +171,8 @@ __global__ void k_cluster_tables(const uint32_t *keys, const uint32_t *vals, con
 
 // posv[v] = v's cluster-major position (its local id plus its cluster's start), -1 for an
 // unassigned vertex (filled beforehand).  u is in cluster c exactly when posv[u] lies in
-// [cl_start[c], cl_start[c+1]), so the compaction gathers one word per entry.
+// [cl_start[c], cl_start[c+1]), so the fill pass gathers one word per entry (the test and
+// the local id at once).
 __global__ void k_cluster_pos(const int32_t *vtx0, const FrontCounts *fc, int32_t *posv) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= fc->na) return;
@@ -182,8 +183,7 @@ __global__ void k_cluster_pos(const int32_t *vtx0, const FrontCounts *fc, int32_
 // deg_in[v] = number of neighbours of v inside v's cluster
 template <typename OT>
 __global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t *idx, int64_t N,
-                                                    int64_t nnz, const int32_t *cidv, const int32_t *posv,
-                                                    const int64_t *cl_start, int32_t *deg_in) {
+                                                    int64_t nnz, const int32_t *cidv, int32_t *deg_in) {
   __shared__ int64_t sh_r[2];
   __shared__ int64_t cache[FROWS];
   __shared__ int cnt[FROWS];
@@ -200,8 +200,7 @@ __global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t
     int64_t v = r0 + r;
     int32_t cv = cidv[v];
     if (cv < 0) continue;
-    int32_t pu = posv[idx[e]];
-    if (pu >= cl_start[cv] && pu < cl_start[cv + 1]) {
+    if (cidv[idx[e]] == cv) {  // (membership alone: the cluster ids, one gather)
       if (cached) atomicAdd(&cnt[r], 1);
       else atomicAdd(&deg_in[v], 1);
     }
@@ -385,10 +384,10 @@ int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
       hipLaunchKernelGGL(k_count_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.posv, cl_start, f.deg_in);
+                         f.N, f.nnz, f.cidv, f.deg_in);
     else
       hipLaunchKernelGGL(k_count_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.posv, cl_start, f.deg_in);
+                         f.N, f.nnz, f.cidv, f.deg_in);
   }
   hipLaunchKernelGGL(k_gather_deg, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, f.deg_in, N,
                      (const FrontCounts *)fc, rd0, rs0);
