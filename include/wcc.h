@@ -117,7 +117,10 @@ typedef struct {
   int64_t mincuts;       /* minimum-cut evaluations */
   int64_t accepted;      /* saved sets */
   int64_t levels;        /* recursion depths (launch rounds) */
-  int64_t scan_steps;    /* maximum-adjacency scan steps over all cuts */
+  int64_t scan_steps;    /* maximum-adjacency scan steps over all cuts (a cut whose
+                            lambda >= bound is certified by edge-disjoint spanning
+                            forests adds none; work counters only, the results do not
+                            depend on which way a cut was found) */
   int64_t scan_rounds;   /* scan-and-contract rounds over all cuts */
   double ms_front;       /* device time: validation, grouping and compaction */
   double ms_items;       /* device time: all item launches */
