@@ -141,6 +141,19 @@ DEV bool uf_link(int32_t *P, int a, int b) {
   }
 }
 
+// a[key] += 1 for every lane with act; the lanes holding the same key as the first active
+// lane share one atomic (counts of a few large groups would otherwise serialise on one
+// address).  Call with the whole wavefront converged.
+DEV void count_agg(int32_t *a, int key, bool act) {
+  uint64_t m = __ballot(act);
+  if (!m) return;
+  int leader = __ffsll((long long)m) - 1;
+  int k0 = __shfl(key, leader, 64);
+  uint64_t same = __ballot(act && key == k0);
+  if (act && key != k0) atomicAdd(&a[key], 1);
+  if ((int)__lane_id() == leader) atomicAdd(&a[k0], (int)__popcll(same));
+}
+
 // Calls f(x, e, y) for every entry e in [0, total) of lists stored in ascending owner
 // order: owner x covers [start[x], end(x)), end(x) = start[x+1] (or total for the last),
 // and y = get(e).  Each thread takes CH consecutive entries.
@@ -395,11 +408,14 @@ DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
   }
   __syncthreads();
   sub_mark(s, 16, &q);
-  for (int i = threadIdx.x; i < n; i += ib()) {
-    if (ld(&s.B[i]) < 0) continue;
-    int r = uf_find(s.B, i);
-    st(&s.B[i], r);
-    atomicAdd(&s.E[r], 1);
+  for (int base = 0; base < n; base += ib()) {
+    int i = base + threadIdx.x;
+    int r = -1;
+    if (i < n && ld(&s.B[i]) >= 0) {
+      r = uf_find(s.B, i);
+      st(&s.B[i], r);
+    }
+    count_agg(s.E, r, r >= 0);
   }
   __syncthreads();
   sub_mark(s, 17, &q);
@@ -446,9 +462,10 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += ib()) st(&s.A[i], 0);
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += ib()) {
-    int L = ldr(&s.B[i]);
-    if (L >= 0) atomicAdd(&s.A[L], 1);
+  for (int base = 0; base < n; base += ib()) {
+    int i = base + threadIdx.x;
+    int L = i < n ? ldr(&s.B[i]) : -1;
+    count_agg(s.A, L, L >= 0);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += ib()) {
