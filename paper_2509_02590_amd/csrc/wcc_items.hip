@@ -827,26 +827,32 @@ DEV bool forest_certificate(const St &s, int t, Sh &sh) {
   return true;
 }
 
-// The same certificate for t <= 4 with all forests built in one pass: forest f keeps its
-// union-find in B, A, D or E (free before the rounds), every vertex first links up to two
-// sampled edges per forest, and then every unused edge joins the first forest whose trees
-// it connects.  One pass over the edges instead of t.
-DEV bool forest_certificate4(const St &s, int t, Sh &sh) {
+// The same certificate for t <= TMAX with all forests built in one pass: forest f keeps
+// its union-find in B, A, D, E, C or F (free before the rounds; TMAX = 4 keeps to the
+// arrays an LDS-state item holds in LDS), every vertex first links up to two sampled edges
+// per forest, and then every unused edge joins the first forest whose trees it connects.
+// One pass over the edges instead of t, but no early stop when a forest cannot span.
+template <int TMAX>
+DEV bool forest_certificate_one(const St &s, int t, Sh &sh) {
   const int n = s.n;
-  auto P = [&](int f) -> int32_t * { return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : s.E; };
+  auto P = [&](int f) -> int32_t * {
+    return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : f == 3 ? s.E : f == 4 ? s.C : s.F;
+  };
   unsigned long long q = s.pf ? wall_clock64() : 0;
   mark_clear(s, s.m);
   for (int x = threadIdx.x; x < n; x += ib()) {
 #pragma unroll
-    for (int f = 0; f < 4; f++)
+    for (int f = 0; f < TMAX; f++)
       if (f < t) st(&P(f)[x], x);
   }
   __syncthreads();
-  int links[4] = {0, 0, 0, 0};
+  int links[TMAX];
+#pragma unroll
+  for (int f = 0; f < TMAX; f++) links[f] = 0;
   for (int x = threadIdx.x; x < n; x += ib()) {
     int r0 = ldr(&s.R[x]), dg = row_end(s, x) - r0;
 #pragma unroll
-    for (int f = 0; f < 4; f++) {
+    for (int f = 0; f < TMAX; f++) {
       if (f >= t) break;
       // two entries of x's row, at a different place for every forest
       int e1 = r0 + (2 * f) % dg, e2 = r0 + (2 * f + 1) % dg;
@@ -865,7 +871,7 @@ DEV bool forest_certificate4(const St &s, int t, Sh &sh) {
   sub_mark(s, 19, &q);
   for (int x = threadIdx.x; x < n; x += ib()) {
 #pragma unroll
-    for (int f = 0; f < 4; f++)
+    for (int f = 0; f < TMAX; f++)
       if (f < t) st(&P(f)[x], uf_find(P(f), x));
   }
   __syncthreads();
@@ -873,7 +879,7 @@ DEV bool forest_certificate4(const St &s, int t, Sh &sh) {
   for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
     if (y <= x || mark_get(s, e)) return;
 #pragma unroll
-    for (int f = 0; f < 4; f++) {
+    for (int f = 0; f < TMAX; f++) {
       if (f >= t) break;
       int32_t *Pf = P(f);
       if (ld(&Pf[x]) != ld(&Pf[y]) && uf_link(Pf, x, y)) {
@@ -884,7 +890,7 @@ DEV bool forest_certificate4(const St &s, int t, Sh &sh) {
   });
   bool ok = true;
 #pragma unroll
-  for (int f = 0; f < 4; f++) {
+  for (int f = 0; f < TMAX; f++) {
     int l = block_sum<IB_MAX>(links[f], sh.red);  // includes barriers
     if (f < t && l < n - 1) ok = false;
   }
@@ -893,6 +899,7 @@ DEV bool forest_certificate4(const St &s, int t, Sh &sh) {
 }
 
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
+template <bool LDS>
 DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, Sh &sh,
                     long long *steps_out, long long *rounds_out) {
   int n = s.n;
@@ -916,8 +923,12 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   // lambda >= bound: no super-vertex degree can fall below the bound, so the rounds would
   // end with (bound, the Phase-0 set); a certificate of it gives the same result at once
   // (bound spanning trees need bound * (n - 1) edges: sparser items skip the attempt)
+  // (one pass for bounds up to 4; above, one pass per forest, which stops at the first
+  // forest that does not span: for items split by a small cut that is cheaper than
+  // checking every forest per edge, most of all when the union-finds are in global memory)
+  constexpr int TONE = 4;
   if (bound > 1 && (long long)s.m / 2 >= (long long)bound * (n - 1) &&
-      (bound <= 4 ? forest_certificate4(s, bound, sh) : forest_certificate(s, bound, sh))) {
+      (bound <= TONE ? forest_certificate_one<TONE>(s, bound, sh) : forest_certificate(s, bound, sh))) {
     if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
     bound = -bound;  // (certified; restored below)
   }
@@ -1203,7 +1214,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
       for (int i = threadIdx.x; i < n; i += ib()) st(&s.F[i], (int32_t)(ld(&s.B[i]) == 0));
       __syncthreads();
     } else {
-      lam = item_mincut(A, s, d, cap, sh, &steps, &rounds);
+      lam = item_mincut<LDS>(A, s, d, cap, sh, &steps, &rounds);
     }
     int64_t p0 = A.split_pos[set];
     for (int i = threadIdx.x; i < n; i += ib()) A.split_side[p0 + i] = (uint8_t)ld(&s.F[i]);
@@ -1242,7 +1253,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   } else if (d.m == 0) {
     return;  // Alg. 3 tests only sets with at least one edge
   }
-  int lam = item_mincut(A, s, d, k, sh, &steps, &rounds);
+  int lam = item_mincut<LDS>(A, s, d, k, sh, &steps, &rounds);
   pt = s.pf ? wall_clock64() : 0;
   // record: |S| and the order-free hash of S's global ids
   int ss = 0;

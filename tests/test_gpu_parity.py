@@ -255,10 +255,12 @@ def test_wcc_global_state_items(exec_mode):
     g = gen.chung_lu(60000, 30.0, 2.5, 11, 2000, 2.0, 0.2, 0.15, 0.05, seed=77, intra_mult=1.8)
     try:
         w.set_exec_config(small_lds_kb=4, big_lds_kb=4, big_max_pct=50)
-        for mode in ("kcore", "paper"):
-            want, wrec = oracle.wcc(g.offsets, g.indices, g.membership, mode=mode)
-            got, st, grec = _run(g.offsets, g.indices, g.membership, mode=mode, exec_mode=exec_mode, graph=False)
-            assert np.array_equal(got, want), mode
+        # (log2 gives bounds of 5-11, which the global-state certificate covers up to 6)
+        for mode, crit in (("kcore", "log10"), ("paper", "log10"), ("kcore", "log2")):
+            want, wrec = oracle.wcc(g.offsets, g.indices, g.membership, mode=mode, criterion=crit)
+            got, st, grec = _run(g.offsets, g.indices, g.membership, mode=mode, criterion=crit,
+                                 exec_mode=exec_mode, graph=False)
+            assert np.array_equal(got, want), (mode, crit)
             assert _rec_key(grec) == _rec_key(wrec)
     finally:
         w.set_exec_config()
