@@ -6,7 +6,8 @@ It shares no code with ``paper_2509_02590_amd``.
 
 What it computes (Dindoost et al., arXiv 2509.02590): CCR (Alg. 1), WCC (Alg. 2) and the
 well-connectedness check isWCC (Alg. 3) with an exact global minimum cut (GetMinCut /
-MinCutPartition, Sec. 2.1) and the criterion f(n) of Sec. 2.  The canonical choice among
+MinCutPartition, Sec. 2.1) and the criterion f(n) of Sec. 2; the Connectivity Modifier
+(CM, Alg. 4, and its check CMC, Alg. 5) with a built-in community detection step.  The canonical choice among
 equal minimum cuts, the integer form of the threshold and the optional KCORE pruning
 mode are documented in ``wcc_oracle.c``.
 """
@@ -25,6 +26,7 @@ _lib = None
 
 CRIT = {"log10": 0, "log2": 1, "sqrt": 2, "linear": 3}
 MODE = {"paper": 0, "kcore": 1}
+CDA = {"components": 0, "labelprop": 1}
 
 RECORD_DTYPE = np.dtype([("minv", np.int32), ("n", np.int32), ("k", np.int32),
                          ("lam", np.int32), ("ssize", np.int32), ("pad", np.int32),
@@ -75,6 +77,11 @@ def _load():
         L.orc_mincut_split.argtypes = [i64, vp, vp, vp, i32, i32, vp]
         L.orc_cluster_csr.restype = i32
         L.orc_cluster_csr.argtypes = [i64, vp, vp, vp] + [ctypes.POINTER(ctypes.c_int64)] * 3 + [vp] * 5
+        L.orc_cm.restype = i32
+        L.orc_cm.argtypes = [i64, vp, vp, vp, ctypes.POINTER(Params), i32, i32, vp, vp, i64,
+                             ctypes.POINTER(ctypes.c_int64), i32]
+        L.orc_cda.restype = i32
+        L.orc_cda.argtypes = [i32, i32, i32, vp, vp, vp]
         L.orc_set_hash.restype = ctypes.c_uint64
         L.orc_set_hash.argtypes = [vp, i64]
         _lib = L
@@ -153,6 +160,44 @@ def wcc(g_or_off, adj=None, membership=None, *, criterion="log10", s_pre=10, s_p
     if log and nlog.value > cap:
         raise RuntimeError("record buffer too small")
     return out[:N], (recs[:nlog.value] if log else None)
+
+
+def cm(g_or_off, adj=None, membership=None, *, cda="components", cda_iters=5, criterion="log10",
+       s_pre=10, s_post=10, lin_num=1, lin_den=1, nthreads=None, log=True):
+    """Full CM (Alg. 4-5) with a built-in CDA -> (membership_out, records)."""
+    if adj is None:
+        g = g_or_off
+        off, adj, membership = g.offsets, g.indices, g.membership
+    else:
+        off = g_or_off
+    off, adj = _csr(off, adj)
+    mem = np.ascontiguousarray(membership, np.int32)
+    N = off.shape[0] - 1
+    out = np.empty(max(N, 1), np.int32)
+    P = params(criterion, s_pre, s_post, "paper", lin_num, lin_den)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    cap = max(2 * N, 16) if log else 0
+    recs = np.zeros(cap, RECORD_DTYPE) if log else None
+    nlog = ctypes.c_int64(0)
+    rc = _load().orc_cm(N, _p(off), _p(adj), _p(mem), ctypes.byref(P), CDA[cda] if isinstance(cda, str) else cda,
+                        cda_iters, _p(out), _p(recs), cap, ctypes.byref(nlog), nthreads)
+    if rc != 0:
+        raise RuntimeError("orc_cm failed: %d" % rc)
+    if log and nlog.value > cap:
+        raise RuntimeError("record buffer too small")
+    return out[:N], (recs[:nlog.value] if log else None)
+
+
+def cda(off, adj, which="labelprop", iters=5):
+    """The CDA alone on a graph of local ids -> (community label per vertex, count)."""
+    off, adj = _csr(off, adj)
+    n = off.shape[0] - 1
+    comm = np.empty(max(n, 1), np.int32)
+    nc = _load().orc_cda(CDA[which] if isinstance(which, str) else which, iters, n, _p(off), _p(adj), _p(comm))
+    if nc < 0:
+        raise RuntimeError("orc_cda failed: %d" % nc)
+    return comm[:n], int(nc)
 
 
 def mincut_split(off, adj, verts, cap: int):

@@ -15,6 +15,8 @@
  *     cut of its induced subgraph is compared with the criterion f(n) of its size n
  *     (Sec. 2: log10 n, log2 n, sqrt n or a linear k*n); "cut > f(n)" accepts the set,
  *     otherwise it is split along the cut and every part larger than s_post recurses.
+ *   - CM (Alg. 4) / CMC (Alg. 5): the same check, but each side of a failing cut is first
+ *     split into communities by a community detection algorithm (CDA); see orc_cm.
  *   - GetMinCut / MinCutPartition (Alg. 3, Sec. 2.1): an exact global minimum cut.  The
  *     paper runs a sequential VieCut variant and does not say which of several equal
  *     cuts it returns; the oracle fixes one canonical cut (see orc_mincut below).
@@ -505,6 +507,8 @@ typedef struct {
   orc_record *log;
   int64_t log_cap, log_n;
   int32_t err;
+  /* Connectivity Modifier (Alg. 4-5) instead of WCC: community detection after splits */
+  int32_t cm, cda, cda_iters;
 } wcc_ctx;
 
 static int push_child(wcc_ctx *c, const int32_t *src, int32_t n) {
@@ -615,6 +619,181 @@ out:
   return rc;
 }
 
+/* ------------------------------------------------------------------ Connectivity Modifier */
+/* The community detection step of Alg. 5 (GetCommunities with a chosen CDA) on the
+ * induced subgraph of one part, local ids 0..n-1.  comm[i] receives the community of i as
+ * a local id; returns the number of communities.
+ *   CDA_COMPONENTS: the connected components (labelled by their smallest vertex).
+ *   CDA_LABELPROP: label propagation (Raghavan, Albert and Kumara 2007) made
+ *     deterministic: every vertex starts with its own id; in each of `iters` synchronous
+ *     rounds every vertex with a neighbour takes the label that occurs most often among
+ *     its neighbours' labels of the previous round, the smallest such label on ties; the
+ *     communities are the classes of equal final labels. */
+enum { CDA_COMPONENTS = 0, CDA_LABELPROP = 1 };
+
+static int cmp_i32(const void *p, const void *q) {
+  int32_t a = *(const int32_t *)p, b = *(const int32_t *)q;
+  return (a > b) - (a < b);
+}
+
+static int32_t cda_communities(int32_t cda, int32_t iters, int32_t n, const int64_t *off,
+                               const int32_t *adj, int32_t *comm) {
+  if (cda == CDA_COMPONENTS) return orc_components(n, off, adj, NULL, comm);
+  int32_t *prev = (int32_t *)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+  int64_t maxdeg = 0;
+  for (int32_t i = 0; i < n; i++)
+    if (off[i + 1] - off[i] > maxdeg) maxdeg = off[i + 1] - off[i];
+  int32_t *nb = (int32_t *)malloc((size_t)(maxdeg ? maxdeg : 1) * sizeof(int32_t));
+  if (!prev || !nb) {
+    free(prev);
+    free(nb);
+    return ORC_ENOMEM;
+  }
+  for (int32_t i = 0; i < n; i++) comm[i] = i;
+  for (int32_t t = 0; t < iters; t++) {
+    memcpy(prev, comm, (size_t)n * sizeof(int32_t));
+    for (int32_t i = 0; i < n; i++) {
+      int64_t d = off[i + 1] - off[i];
+      if (d == 0) continue;
+      for (int64_t e = 0; e < d; e++) nb[e] = prev[adj[off[i] + e]];
+      qsort(nb, (size_t)d, sizeof(int32_t), cmp_i32);
+      /* longest run of equal labels; the first (smallest) label wins a tie */
+      int32_t best = nb[0];
+      int64_t best_len = 0;
+      for (int64_t a = 0; a < d;) {
+        int64_t b = a;
+        while (b < d && nb[b] == nb[a]) b++;
+        if (b - a > best_len) {
+          best_len = b - a;
+          best = nb[a];
+        }
+        a = b;
+      }
+      comm[i] = best;
+    }
+  }
+  /* number of distinct labels */
+  memcpy(prev, comm, (size_t)n * sizeof(int32_t));
+  qsort(prev, (size_t)n, sizeof(int32_t), cmp_i32);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; i++) nc += (i == 0 || prev[i] != prev[i - 1]);
+  free(prev);
+  free(nb);
+  return nc;
+}
+
+/* One queued set of CM (the CMC check of Alg. 5): a set with at least one edge is
+ * saved when its canonical cut reaches k(n); otherwise each side of the cut larger than
+ * s_post is handed to the CDA, and either each of its communities larger than s_post
+ * (when there are several) or the whole part (when there is one, "processed as a single
+ * unit") is checked again.  A disconnected set (only a CDA community can be one) has
+ * cut 0 with S = the component of its smallest vertex.  No pruning: CM as printed. */
+static int cm_item(wcc_ctx *c, item it, lgraph *H, ivec *tmp) {
+  const orc_params *P = &c->P;
+  int32_t n = it.n;
+  if (induced(c->off, c->idx, c->lmap, it.v, n, H)) return ORC_ENOMEM;
+  if (H->off[n] == 0) return ORC_OK; /* |E_c| = 0: nothing to test */
+  int32_t k = (int32_t)orc_threshold(P->criterion, n, P->lin_num, P->lin_den);
+  int rc = ORC_OK;
+  uint8_t *side = (uint8_t *)malloc((size_t)n);
+  int32_t *comp = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *part = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  lgraph Hp = {0};
+  if (!side || !comp || !part) {
+    rc = ORC_ENOMEM;
+    goto out;
+  }
+  int32_t lam;
+  if (orc_components(n, H->off, H->adj, NULL, comp) > 1) {
+    lam = 0;
+    for (int32_t i = 0; i < n; i++) side[i] = comp[i] == 0;
+  } else {
+    lam = orc_mincut(n, H->off, H->adj, k, side);
+    if (lam < 0) {
+      rc = lam;
+      goto out;
+    }
+  }
+  {
+    orc_record rec = {it.v[0], n, k, lam, 0, 0, 0};
+    for (int32_t i = 0; i < n; i++)
+      if (side[i]) {
+        rec.ssize++;
+        rec.shash += vhash(it.v[i]);
+      }
+    pthread_mutex_lock(&c->lock);
+    if (c->log && c->log_n < c->log_cap) c->log[c->log_n] = rec;
+    c->log_n++;
+    pthread_mutex_unlock(&c->lock);
+  }
+  if (lam >= k) { /* cut > criterion: save the set */
+    int32_t *v = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!v) {
+      rc = ORC_ENOMEM;
+      goto out;
+    }
+    memcpy(v, it.v, (size_t)n * sizeof(int32_t));
+    pthread_mutex_lock(&c->lock);
+    int r = il_push(&c->accepted, (item){v, n});
+    pthread_mutex_unlock(&c->lock);
+    if (r) {
+      free(v);
+      rc = ORC_ENOMEM;
+    }
+    goto out;
+  }
+  for (int sd = 1; sd >= 0; sd--) {
+    int32_t np = 0;
+    for (int32_t i = 0; i < n; i++)
+      if (side[i] == sd) part[np++] = it.v[i];
+    if (np <= P->s_post) continue;
+    if (induced(c->off, c->idx, c->lmap, part, np, &Hp)) {
+      rc = ORC_ENOMEM;
+      goto out;
+    }
+    int32_t nc = cda_communities(c->cda, c->cda_iters, np, Hp.off, Hp.adj, comp);
+    if (nc < 0) {
+      rc = nc;
+      goto out;
+    }
+    if (nc <= 1) {
+      if (push_child(c, part, np)) {
+        rc = ORC_ENOMEM;
+        goto out;
+      }
+      continue;
+    }
+    /* each community V_i (ascending ids) larger than s_post */
+    for (int32_t r = 0; r < np; r++) {
+      int32_t lab = comp[r];
+      int first = 1;
+      for (int32_t i = 0; i < r; i++)
+        if (comp[i] == lab) {
+          first = 0;
+          break;
+        }
+      if (!first) continue;
+      tmp->n = 0;
+      for (int32_t i = r; i < np; i++)
+        if (comp[i] == lab && iv_push(tmp, part[i])) {
+          rc = ORC_ENOMEM;
+          goto out;
+        }
+      if (tmp->n > P->s_post && push_child(c, tmp->a, (int32_t)tmp->n)) {
+        rc = ORC_ENOMEM;
+        goto out;
+      }
+    }
+  }
+out:
+  free(side);
+  free(comp);
+  free(part);
+  free(Hp.off);
+  free(Hp.adj);
+  return rc;
+}
+
 static void *worker(void *arg) {
   wcc_ctx *c = (wcc_ctx *)arg;
   lgraph H = {0};
@@ -622,7 +801,7 @@ static void *worker(void *arg) {
   for (;;) {
     int64_t i = __atomic_fetch_add(&c->next_item, 1, __ATOMIC_RELAXED);
     if (i >= c->cur->n) break;
-    int rc = process_item(c, c->cur->a[i], &H, &tmp);
+    int rc = c->cm ? cm_item(c, c->cur->a[i], &H, &tmp) : process_item(c, c->cur->a[i], &H, &tmp);
     if (rc) {
       pthread_mutex_lock(&c->lock);
       if (!c->err) c->err = rc;
@@ -686,13 +865,16 @@ static int check_params(const orc_params *P) {
  *   *log_n receives the total count.  Items are processed level by level with
  *   nthreads threads; the result does not depend on the order.
  */
-int32_t orc_wcc(int64_t N, const int64_t *off, const int32_t *idx, const int32_t *membership,
-                const orc_params *P, int32_t *out, orc_record *log, int64_t log_cap,
-                int64_t *log_n, int32_t nthreads) {
+static int32_t orc_drive(int64_t N, const int64_t *off, const int32_t *idx, const int32_t *membership,
+                         const orc_params *P, int32_t *out, orc_record *log, int64_t log_cap,
+                         int64_t *log_n, int32_t nthreads, int32_t cm, int32_t cda, int32_t cda_iters) {
   int32_t rc = check_params(P);
   if (rc) return rc;
   wcc_ctx c;
   memset(&c, 0, sizeof(c));
+  c.cm = cm;
+  c.cda = cda;
+  c.cda_iters = cda_iters;
   c.N = N;
   c.off = off;
   c.idx = idx;
@@ -801,6 +983,31 @@ done:
   free(pairs);
   pthread_mutex_destroy(&c.lock);
   return rc;
+}
+
+int32_t orc_wcc(int64_t N, const int64_t *off, const int32_t *idx, const int32_t *membership,
+                const orc_params *P, int32_t *out, orc_record *log, int64_t log_cap,
+                int64_t *log_n, int32_t nthreads) {
+  return orc_drive(N, off, idx, membership, P, out, log, log_cap, log_n, nthreads, 0, 0, 0);
+}
+
+/*
+ * Full CM (Alg. 4 with CCR, Alg. 1, and the check CMC, Alg. 5) with a built-in CDA
+ * (CDA_COMPONENTS, or CDA_LABELPROP with cda_iters rounds).  P->prune_mode is ignored
+ * (CM as printed prunes nothing).  Outputs as orc_wcc: canonical labels of the saved
+ * sets and one record per minimum-cut evaluation.
+ */
+int32_t orc_cm(int64_t N, const int64_t *off, const int32_t *idx, const int32_t *membership,
+               const orc_params *P, int32_t cda, int32_t cda_iters, int32_t *out, orc_record *log,
+               int64_t log_cap, int64_t *log_n, int32_t nthreads) {
+  if ((cda != CDA_COMPONENTS && cda != CDA_LABELPROP) || cda_iters < 0) return ORC_EINVAL;
+  return orc_drive(N, off, idx, membership, P, out, log, log_cap, log_n, nthreads, 1, cda, cda_iters);
+}
+
+/* The CDA alone on a graph (local ids): comm[i] = community label; returns their count. */
+int32_t orc_cda(int32_t cda, int32_t iters, int32_t n, const int64_t *off, const int32_t *adj, int32_t *comm) {
+  if ((cda != CDA_COMPONENTS && cda != CDA_LABELPROP) || iters < 0) return ORC_EINVAL;
+  return cda_communities(cda, iters, n, off, adj, comm);
 }
 
 /*
