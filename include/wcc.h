@@ -90,7 +90,10 @@ typedef struct {
                               as a HIP graph and replayed when called again with the same
                               buffers and parameters */
 
-#define WCC_FLAG_VALIDATE 1u /* check the CSR first; WCC_EGRAPH if malformed */
+#define WCC_FLAG_VALIDATE 1u /* check the CSR first: offsets non-decreasing from 0 to
+                                num_entries, ids in [0, N), no self-loop, no entry repeated
+                                in its row, every entry matched by its reverse; WCC_EGRAPH
+                                if any check fails */
 #define WCC_FLAG_NO_GRAPH 2u /* BATCHED: neither record nor replay a HIP graph */
 
 typedef struct {
@@ -160,8 +163,7 @@ typedef struct {
  *                  when it exceeds records_cap (then only the first records_cap are kept).
  * Errors: WCC_EINVAL (NULL required pointers, s_pre/s_post < 0, bad criterion, N < 0 or
  * num_entries inconsistent with offsets), WCC_EGRAPH (with WCC_FLAG_VALIDATE),
- * WCC_ENOMEM, WCC_EHIP, WCC_EUNSUPPORTED (a cluster with more than 2^24 vertices, or a
- * cut bound above 62 for SQRT/LINEAR criteria).
+ * WCC_ENOMEM, WCC_EHIP, WCC_EUNSUPPORTED (a cluster with more than 2^24 - 1 vertices).
  */
 int wcc_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p,
             int32_t *membership_out, wcc_stats *stats, wcc_record *records, int64_t records_cap,
@@ -172,13 +174,13 @@ int wcc_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p,
  * subgraph of G induced by one vertex set.
  *   verts   device, n int32 global ids, sorted ascending, unique.
  *   cap     >= 1: the cut is exact when its value is below cap; otherwise cap is
- *           returned (pass INT32_MAX for an uncapped exact cut; WCC uses k(n)).
+ *           returned (pass INT32_MAX for an uncapped exact cut, of any value; WCC uses
+ *           k(n)).
  *   lambda  host, out: the cut value (0 if the induced subgraph is disconnected or n < 2).
  *   side    device, n bytes, out: 1 for vertices in S.  A disconnected set returns S =
  *           the component of verts[0]; n < 2 returns S empty.
  * Errors: WCC_EINVAL (unsorted/duplicate/out-of-range verts are checked on the device),
- * WCC_ENOMEM, WCC_EHIP, WCC_EUNSUPPORTED (cap above 62 while the set's minimum degree
- * also exceeds 62).
+ * WCC_ENOMEM, WCC_EHIP, WCC_EUNSUPPORTED (a set with more than 2^24 - 1 vertices).
  */
 int wcc_mincut_split(const wcc_csr *g, const int32_t *verts, int32_t n, int32_t cap,
                      int32_t *lambda, uint8_t *side, void *stream);
@@ -222,6 +224,71 @@ int wcc_cluster_csr(const wcc_csr *g, const int32_t *membership_in, int64_t *ncl
  * Blocks until comp_out is complete.  Errors: WCC_EINVAL, WCC_ENOMEM, WCC_EHIP.
  */
 int wcc_ccr_components(const wcc_csr *g, const int32_t *membership_in, int32_t *comp_out, void *stream);
+
+/* ------------------------------------------------------------------ Connectivity Modifier */
+/* The community detection step of CM (GetCommunities with a CDA, Alg. 5).  Built in:
+ *   WCC_CDA_COMPONENTS  the connected components of each part;
+ *   WCC_CDA_LABELPROP   label propagation with ties broken deterministically: every vertex
+ *                       starts with its own id as label; in each of cda_iters synchronous
+ *                       rounds every vertex with a neighbour in its part takes the label that
+ *                       occurs most often among those neighbours' labels of the previous
+ *                       round, the smallest such label on ties; communities are the classes
+ *                       of equal final labels;
+ *   WCC_CDA_CALLBACK    the caller's function (e.g. a Leiden implementation). */
+#define WCC_CDA_COMPONENTS 0
+#define WCC_CDA_LABELPROP 1
+#define WCC_CDA_CALLBACK 2
+
+/* A caller-supplied CDA.  part_of: device, N int32: the part of every vertex (a label
+ * >= 0; vertices with equal labels form one part) or -1.  comm_out: device, N int32,
+ * prefilled with -1: the callback writes a community label (any int32 >= 0) for every
+ * vertex of a part; vertices of one part with equal labels form one community, and
+ * communities are formed inside each part only.  The callback enqueues its work on
+ * `stream` (a hipStream_t as void*) or completes it before returning, and returns
+ * WCC_OK or a negative WCC_E* code, which wcc_cm_run then returns.  It must not call
+ * back into this library (the calling thread holds the library's device lock). */
+typedef int (*wcc_cda_fn)(const wcc_csr *g, const int32_t *part_of, int32_t *comm_out, void *user, void *stream);
+
+typedef struct {
+  int32_t cda;       /* WCC_CDA_* */
+  int32_t cda_iters; /* LABELPROP: synchronous rounds, 0..1000 */
+  wcc_cda_fn fn;     /* CALLBACK: the function */
+  void *user;        /* CALLBACK: passed through unchanged */
+} wcc_cm_params;
+
+/*
+ * wcc_cm_run -- the Connectivity Modifier (CM, Alg. 4, with its check CMC, Alg. 5) over a
+ * whole graph and input clustering.  CCR (Alg. 1) first; then every queued set with at
+ * least one edge gets the canonical minimum cut capped at k(n) (as in wcc_run) and is
+ * saved when the cut reaches k(n).  Otherwise each side of the cut with more than s_post
+ * vertices is split into communities by the CDA: when there are several, every community
+ * with more than s_post vertices is checked again; when there is one, the whole side is
+ * checked again ("processed as a single unit").  A disconnected set (a CDA community can
+ * be one) has cut 0 and S = the component of its smallest vertex.  CM prunes nothing:
+ * p->prune_mode and p->exec_mode are ignored.
+ *   g, membership_in, membership_out, stats, records, records_cap, num_records: as for
+ *   wcc_run (labels: saved sets by ascending smallest vertex, others -1; one record per
+ *   minimum-cut evaluation).  stats carries clusters = 0, items = mincuts, accepted,
+ *   levels and ms_total.
+ *   cm   host: the CDA (see above).
+ * Errors: WCC_EINVAL (bad arguments or CDA parameters), WCC_EGRAPH (WCC_FLAG_VALIDATE),
+ * WCC_ENOMEM, WCC_EHIP, a callback's own error code.
+ */
+int wcc_cm_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, const wcc_cm_params *cm,
+               int32_t *membership_out, wcc_stats *stats, wcc_record *records, int64_t records_cap,
+               int64_t *num_records, void *stream);
+
+/*
+ * wcc_cda -- one built-in CDA step alone on parts of G (the GetCommunities call of Alg. 5):
+ * comm_out[v] = the community label of v (a global vertex id of v's part: the smallest
+ * vertex of v's component, or v's final label-propagation label), -1 for v in no part.
+ *   part_of   device, N int32 (labels >= 0 or -1)
+ *   cm        host: WCC_CDA_COMPONENTS or WCC_CDA_LABELPROP
+ *   comm_out  device, N int32, caller-allocated
+ * Blocks until comm_out is complete.  Errors: WCC_EINVAL (also for WCC_CDA_CALLBACK),
+ * WCC_ENOMEM, WCC_EHIP.
+ */
+int wcc_cda(const wcc_csr *g, const int32_t *part_of, const wcc_cm_params *cm, int32_t *comm_out, void *stream);
 
 /* Threshold k(n) used by the library for the given criterion (host function). */
 int64_t wcc_threshold(int32_t criterion, int64_t n, int32_t lin_num, int32_t lin_den);

@@ -130,6 +130,21 @@ lib.wcc_get_exec_config.argtypes = [ctypes.POINTER(ExecConfig)]
 lib.wcc_set_exec_config.restype = ctypes.c_int
 lib.wcc_set_exec_config.argtypes = [ctypes.POINTER(ExecConfig)]
 lib.wcc_last_error_detail.restype = ctypes.c_char_p
+
+CDA = {"components": 0, "labelprop": 1, "callback": 2}
+# int (*)(const wcc_csr *g, const int32_t *part_of, int32_t *comm_out, void *user, void *stream)
+CDA_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(Csr), _vp, _vp, _vp, _vp)
+
+
+class CmParams(ctypes.Structure):
+    _fields_ = [("cda", ctypes.c_int32), ("cda_iters", ctypes.c_int32), ("fn", CDA_FN), ("user", _vp)]
+
+
+lib.wcc_cm_run.restype = ctypes.c_int
+lib.wcc_cm_run.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(Params), ctypes.POINTER(CmParams), _vp,
+                           ctypes.POINTER(Stats), _vp, _i64, ctypes.POINTER(ctypes.c_int64), _vp]
+lib.wcc_cda.restype = ctypes.c_int
+lib.wcc_cda.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(CmParams), _vp, _vp]
 lib.wcc_abi_version.restype = ctypes.c_int
 
 
@@ -337,6 +352,69 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _cm_params(cda, cda_iters, callback):
+    c = CmParams()
+    c.cda = CDA[cda] if isinstance(cda, str) else cda
+    c.cda_iters = cda_iters
+    fn = None
+    if callback is not None:
+        c.cda = CDA["callback"]
+        # callback(num_vertices, part_of_ptr, comm_out_ptr, stream_ptr) -> 0 or a WCC error code
+        def tramp(g, part_of, comm_out, user, stream):
+            try:
+                return int(callback(g.contents.num_vertices, part_of, comm_out, stream))
+            except Exception:
+                return -1
+        fn = CDA_FN(tramp)
+        c.fn = fn
+    return c, fn
+
+
+def cm_run(offsets, indices, membership, *, cda="labelprop", cda_iters=5, callback=None, out=None,
+           records_cap=0, **kw):
+    """The Connectivity Modifier (CM with its check CMC) -> (membership_out, Stats, records).
+    callback(num_vertices, part_of_ptr, comm_out_ptr, stream_ptr) supplies a CDA of the
+    caller's own (device pointers as ints); it must not call into the library."""
+    import torch
+    g = make_csr(offsets, indices)
+    assert membership.is_cuda and membership.dtype == torch.int32 and membership.numel() == g.num_vertices
+    if out is None:
+        out = torch.empty_like(membership)
+    p = params(**kw)
+    c, keep = _cm_params(cda, cda_iters, callback)
+    st = Stats()
+    rec = None
+    nrec = ctypes.c_int64(0)
+    if records_cap:
+        rec = torch.empty(records_cap * RECORD_DTYPE.itemsize, dtype=torch.uint8, device=membership.device)
+    rc = lib.wcc_cm_run(ctypes.byref(g), membership.data_ptr() if membership.numel() else None, ctypes.byref(p),
+                        ctypes.byref(c), out.data_ptr() if out.numel() else None, ctypes.byref(st),
+                        rec.data_ptr() if rec is not None else None, records_cap, ctypes.byref(nrec),
+                        _stream(torch, membership.device))
+    del keep
+    _check(rc, "wcc_cm_run")
+    records = None
+    if rec is not None:
+        k = min(nrec.value, records_cap)
+        records = np.frombuffer(rec[:k * RECORD_DTYPE.itemsize].cpu().numpy().tobytes(), RECORD_DTYPE)
+        if nrec.value > records_cap:
+            raise WccError(-3, "records buffer too small (%d needed)" % nrec.value)
+    return out, st, records
+
+
+def cda(offsets, indices, part_of, which="labelprop", iters=5, out=None):
+    """A built-in CDA alone on the parts of part_of -> device int32 community labels."""
+    import torch
+    g = make_csr(offsets, indices)
+    if out is None:
+        out = torch.empty_like(part_of)
+    c, _ = _cm_params(which, iters, None)
+    rc = lib.wcc_cda(ctypes.byref(g), part_of.data_ptr() if part_of.numel() else None, ctypes.byref(c),
+                     out.data_ptr() if out.numel() else None, _stream(torch, part_of.device))
+    _check(rc, "wcc_cda")
+    return out
 
 
 def ccr_components(offsets, indices, membership, out=None):

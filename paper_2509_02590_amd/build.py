@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libwcc.so")
-SOURCES = ["wcc_prims.hip", "wcc_front.hip", "wcc_items.hip", "wcc_capi.hip"]
+SOURCES = ["wcc_prims.hip", "wcc_front.hip", "wcc_items.hip", "wcc_cm.hip", "wcc_capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -65,6 +65,11 @@ enum BufId {
   B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SG, B_SEDGE, B_SMARK, B_GBITS,
   B_ITEMS0, B_ITEMS1, B_ITEMS_SORTED, B_SET0, B_SET_SORTED, B_IKEYS, B_IVALS, B_IKEYS2, B_IVALS2,
   B_SPLITMEM, B_SMALL, B_LVCTL, B_LB0, B_LB1, B_LBS,
+  // Connectivity Modifier: per vertex, per set, per run, and label propagation per entry
+  B_CM_CUR, B_CM_PART, B_CM_COMM, B_CM_ACC, B_CM_SETOF, B_CM_VERTS, B_CM_SETIDX, B_CM_FLAG, B_CM_FSCAN,
+  B_CM_K1, B_CM_V1, B_CM_K2, B_CM_V2, B_CM_NCOMM, B_CM_SO, B_CM_CAPS, B_CM_HASE, B_CM_SSZ, B_CM_SHASH,
+  B_CM_LAM, B_CM_PSZ, B_CM_PMIN, B_CM_SIDES, B_CM_RUNF, B_CM_RUNS, B_CM_RUNSTART, B_CM_RUNSIZE, B_CM_CTL,
+  B_CM_TMP, B_LP_EROW, B_LP_ENB, B_LP_LAB, B_LP_LAB2, B_LP_K1, B_LP_V1, B_LP_K2, B_LP_V2, B_LP_TMP,
   B_NUM
 };
 
@@ -94,7 +99,8 @@ struct GraphKey {
 
 // Sizes a batched run was planned with (host side).
 struct BatchPlan {
-  int32_t nitems = 0, nbig = 0, top_n = 0, small_max = 0;
+  int32_t nitems = 0, nbig = 0, top_n = 0;
+  int64_t small_words = 0;
   size_t lds_bytes = 0, big_bytes = 0;
   int g_big = 0, g_small = 0;
   int64_t gbits_words = 0;
@@ -236,7 +242,7 @@ int check_csr(const wcc_csr *g) {
 // compaction; the sizes it produced stay on the device in FrontCounts.
 int ensure_items(Workspace &w, int64_t cap, bool with_sets);
 
-int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate, bool want_ids, bool all_items,
+int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool want_ids, bool all_items,
               hipStream_t s) {
   int64_t N = g->num_vertices;
   size_t n4 = (size_t)(N > 0 ? N : 1) * 4;
@@ -280,11 +286,6 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
   f.tmp_bytes = w.b[B_TMP].bytes;
   f.dcnt = w.b[B_DCNT].as<unsigned long long>();
   f.dmax = (int32_t *)(f.dcnt + 8);
-  if (validate) {
-    int ok = 1;
-    TRY(front_validate(f, s, &ok));
-    if (!ok) return WCC_EGRAPH;
-  }
   if (w.b[B_DCNT].bytes == 0) return WCC_EINVAL;
   return front_build(f, front_counts(w), w.b[B_VTX0].as<int32_t>(), w.b[B_CLSTART].as<int64_t>(),
                      want_ids ? w.b[B_CLIDS].as<int32_t>() : nullptr, w.b[B_RD0].as<int32_t>(),
@@ -295,6 +296,11 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool validate,
 // CSR checks only (symmetric, simple, ids in range): WCC_EGRAPH when malformed.
 int run_validate(Workspace &w, const wcc_csr *g, hipStream_t s) {
   TRY(w.b[B_DCNT].ensure(256 * sizeof(unsigned long long)));
+  // the duplicate tables borrow the second arena and the crossing-list scratch (sized as
+  // the front end sizes them anyway)
+  size_t e4 = (size_t)(g->num_entries > 0 ? g->num_entries : 1) * 4;
+  TRY(w.b[B_ADJ1].ensure(e4));
+  TRY(w.b[B_SEDGE].ensure(e4));
   FrontBufs f;
   memset(&f, 0, sizeof(f));
   f.off = g->row_offsets;
@@ -303,6 +309,8 @@ int run_validate(Workspace &w, const wcc_csr *g, hipStream_t s) {
   f.N = g->num_vertices;
   f.nnz = g->num_entries;
   f.dcnt = w.b[B_DCNT].as<unsigned long long>();
+  f.vtab_a = w.b[B_ADJ1].as<int32_t>();
+  f.vtab_b = w.b[B_SEDGE].as<int32_t>();
   int ok = 1;
   TRY(front_validate(f, s, &ok));
   return ok ? WCC_OK : WCC_EGRAPH;
@@ -318,17 +326,39 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Largest n whose item state fits `words` 32-bit LDS words (cap from the criterion).
-int small_max_n(int64_t words, int crit, const wcc_params &p, bool split) {
-  int64_t lo = 0, hi = 1 << 24;
+// Smallest n whose scan state can exceed `words` 32-bit LDS words: an item of n vertices
+// has at most n(n-1) list entries, and its cut cap is k(n) of the criterion (WCC) or any
+// caller's cap (mincut_split).  Items of one level are disjoint, so at most N / that many
+// of them are large.
+int min_big_n(int64_t words, const wcc_params &p, bool split) {
+  int64_t lo = 1, hi = 1 << 24;
   while (lo < hi) {
-    int64_t mid = (lo + hi + 1) / 2;
-    int cap = split ? items_max_level() : (int)wcc_k_of(crit, mid, p.lin_num, p.lin_den);
-    if (items_lds_words(mid, cap) <= words) lo = mid;
-    else hi = mid - 1;
+    int64_t mid = (lo + hi) / 2;
+    int64_t cap = split ? (int64_t)INT32_MAX : wcc_k_of(p.criterion, mid, p.lin_num, p.lin_den);
+    if (item_state_words(mid, mid * (mid - 1), cap) > words) hi = mid;
+    else lo = mid + 1;
   }
   return (int)lo;
 }
+
+// Device words of a level's sort: [0] large-item count, [2..3] largest bitmap (64-bit)
+int32_t *sort_sizes(Workspace &w) { return (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 20); }
+
+SortNeed sort_need(const wcc_params &p, const ItemArgs &base, int64_t small_words) {
+  SortNeed nd;
+  nd.crit = p.criterion;
+  nd.lin_num = p.lin_num;
+  nd.lin_den = p.lin_den;
+  nd.caps = base.split_only ? base.split_cap : nullptr;
+  nd.set = nullptr;
+  nd.small_words = small_words;
+  return nd;
+}
+
+struct SortSizes {
+  int32_t nbig, pad;
+  int64_t maxbits;
+};
 
 // Processes item lists level by level until no children remain.  Each level is sorted
 // by size (largest first) and split into two launches that run concurrently: the items
@@ -367,11 +397,12 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
   int32_t *dcount = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16);
   int32_t *dnext = dcount + 1;
   int32_t *dnext_big = dcount + 2;
-  int32_t *dnbig = dcount + 3;
+  int32_t *dsz = sort_sizes(w);
   ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
   int32_t *set_sorted = base.split_only ? w.b[B_SET_SORTED].as<int32_t>() : nullptr;
   const int32_t *set_in = base.split_only ? w.b[B_SET0].as<int32_t>() : nullptr;
-  int small_max = small_max_n((int64_t)(lds_bytes / 4), max_cap_crit, p, base.split_only);
+  SortNeed nd = sort_need(p, base, (int64_t)(lds_bytes / 4));
+  (void)max_cap_crit;
   *levels = 0;
   *ms_kernel = 0;
   *launches = 0;
@@ -380,18 +411,18 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     ItemDesc *out = w.b[cur ? B_ITEMS0 : B_ITEMS1].as<ItemDesc>();
     TRY(items_sort_desc(in, nitems, sorted, set_in, set_sorted, w.b[B_IKEYS].as<uint32_t>(),
                         w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(), w.b[B_IVALS2].as<uint32_t>(),
-                        w.b[B_TMP].p, w.b[B_TMP].bytes, s, small_max, dnbig));
+                        w.b[B_TMP].p, w.b[B_TMP].bytes, s, nd, dsz));
     ItemDesc top;
-    int32_t nbig = 0;
+    SortSizes hs;
     HIP_TRY(hipMemcpyAsync(&top, sorted, sizeof(top), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&nbig, dnbig, sizeof(nbig), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hs, dsz, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    int32_t nbig = hs.nbig;
     int32_t nsmall = nitems - nbig;
     int grid_small = nsmall < gmax ? nsmall : gmax;
     int grid_big = nbig < w.cus ? nbig : w.cus;
-    int cap_top = base.split_only ? items_max_level()
-                                  : (int)wcc_k_of(max_cap_crit, top.n, p.lin_num, p.lin_den);
-    int64_t words = items_bitmap_words(top.n, cap_top);
+    // bitmap regions of the large-bin workgroups (small-bin items keep their state in LDS)
+    int64_t words = hs.maxbits > 0 ? hs.maxbits : 1;
     TRY(w.b[B_GBITS].ensure((size_t)(grid_big > 0 ? grid_big : 1) * words * 8 + 64));
     ItemArgs A = base;
     A.gbits = w.b[B_GBITS].as<uint64_t>();
@@ -420,6 +451,7 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       Sm.nitems = nsmall;
       Sm.next = dnext;
       Sm.lds_words = (int32_t)(lds_bytes / 4);
+      Sm.gbits_words = 0;  // (small-bin items keep their scan state in LDS)
       if (base.split_only) Sm.split_set = set_sorted + nbig;
       HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
       HIP_TRY(hipEventRecord(w.evs0, w.s2));
@@ -475,20 +507,27 @@ int plan_batched(Workspace &w, const wcc_params &p, int64_t N, int32_t nitems, B
   pl->nitems = nitems;
   pl->lds_bytes = shp.lds_bytes;
   pl->big_bytes = shp.big_bytes;
-  pl->small_max = small_max_n((int64_t)(shp.lds_bytes / 4), p.criterion, p, false);
-  int32_t *dnbig = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16) + 3;
+  pl->small_words = (int64_t)(shp.lds_bytes / 4);
+  int32_t *dsz = sort_sizes(w);
   ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
   pl->nbig = 0;
   pl->top_n = 0;
+  int64_t maxbits = 1;
   if (nitems > 0) {
+    ItemArgs none;
+    memset(&none, 0, sizeof(none));
     TRY(items_sort_desc(w.b[B_ITEMS0].as<ItemDesc>(), nitems, sorted, nullptr, nullptr,
                         w.b[B_IKEYS].as<uint32_t>(), w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(),
-                        w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p, w.b[B_TMP].bytes, s, pl->small_max, dnbig));
+                        w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p, w.b[B_TMP].bytes, s,
+                        sort_need(p, none, pl->small_words), dsz));
     ItemDesc top;
+    SortSizes hs;
     HIP_TRY(hipMemcpyAsync(&top, sorted, sizeof(top), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&pl->nbig, dnbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hs, dsz, sizeof(hs), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     pl->top_n = top.n;
+    pl->nbig = hs.nbig;
+    maxbits = hs.maxbits > 0 ? hs.maxbits : 1;
   }
   // Both bins are launched oversubscribed, as in the plain form: a workgroup leaves as soon
   // as its list is empty, so CUs freed by one bin go to the other.  Large-bin workgroups:
@@ -499,28 +538,37 @@ int plan_batched(Workspace &w, const wcc_params &p, int64_t N, int32_t nitems, B
   pl->g_big = pl->nbig < cap_big ? pl->nbig : cap_big;
   if (pl->g_big == 0) pl->nbig = 0;
   pl->g_small = w.cus * shp.per_cu;
-  int cap_top = (int)wcc_k_of(p.criterion, pl->top_n > 0 ? pl->top_n : 1, p.lin_num, p.lin_den);
-  pl->gbits_words = items_bitmap_words(pl->top_n > 0 ? pl->top_n : 1, cap_top);
-  // the items of one level are disjoint vertex sets; large ones have > small_max vertices
+  // (the bitmap bound of the initial items covers their descendants: smaller sets with
+  // caps no larger)
+  pl->gbits_words = maxbits;
   pl->capS = N + 1;
-  pl->capB = N / ((int64_t)pl->small_max + 1) + 1;
+  pl->capB = N / min_big_n(pl->small_words, p, false) + 1;
   TRY(w.b[B_LVCTL].ensure((size_t)items_level_words() * 4));
   TRY(w.b[B_LB0].ensure((size_t)pl->capB * sizeof(ItemDesc)));
   TRY(w.b[B_LB1].ensure((size_t)pl->capB * sizeof(ItemDesc)));
   TRY(w.b[B_LBS].ensure((size_t)pl->capB * sizeof(ItemDesc)));
-  TRY(w.b[B_GBITS].ensure((size_t)(pl->g_big + pl->g_small) * pl->gbits_words * 8 + 64));
+  // global-state items run in large-bin workgroups only (children whose state exceeds the
+  // small-bin LDS go to the large lists), unless there is no large-bin launch
+  TRY(w.b[B_GBITS].ensure((size_t)(pl->g_big > 0 ? pl->g_big : pl->g_small) * pl->gbits_words * 8 + 64));
   return WCC_OK;
 }
 
 // Level 0 input: the sorted initial items split into the parity-0 lists.  guard: the
 // device checks its sizes against the plan (a recorded sequence replayed on new data).
 int route_level0(Workspace &w, const ItemArgs &base, const BatchPlan &pl, bool sort, bool guard, hipStream_t s) {
-  int32_t *dnbig = (int32_t *)(w.b[B_DCNT].as<unsigned long long>() + 16) + 3;
+  int32_t *dnbig = sort_sizes(w);
   ItemDesc *sorted = w.b[B_ITEMS_SORTED].as<ItemDesc>();
-  if (sort && pl.nitems > 0)
+  if (sort && pl.nitems > 0) {
+    wcc_params p;
+    wcc_default_params(&p);
+    p.criterion = base.crit;
+    p.lin_num = base.lin_num;
+    p.lin_den = base.lin_den;
     TRY(items_sort_desc(w.b[B_ITEMS0].as<ItemDesc>(), pl.nitems, sorted, nullptr, nullptr,
                         w.b[B_IKEYS].as<uint32_t>(), w.b[B_IVALS].as<uint32_t>(), w.b[B_IKEYS2].as<uint32_t>(),
-                        w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p, w.b[B_TMP].bytes, s, pl.small_max, dnbig));
+                        w.b[B_IVALS2].as<uint32_t>(), w.b[B_TMP].p, w.b[B_TMP].bytes, s,
+                        sort_need(p, base, pl.small_words), dnbig));
+  }
   if (pl.g_big == 0 && pl.nitems > 0) TRY(prim_fill32(dnbig, 0u, 1, s));  // everything small
   return items_route0(sorted, pl.nitems, dnbig, front_counts(w), guard ? pl.nitems : -1, pl.nbig, pl.top_n,
                       list_small(w, 0), list_big(w, 0), level_ctl(w), base.cnt, s);
@@ -543,7 +591,7 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
     A.out_big = pl.g_big > 0 ? list_big(w, nx) : nullptr;
     A.out_big_count = ctl + 2 * nx + 1;
     A.out_big_cap = (int32_t)pl.capB;
-    A.small_max = pl.small_max;
+    A.small_words = pl.small_words;
     A.gbits_words = pl.gbits_words;
     if (pl.g_big > 0) {
       // largest first (level 0 is sorted already) so that the longest items start at once;
@@ -575,7 +623,8 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
     Sm.nitems = (int32_t)pl.capS;
     Sm.next = ctl + items_level_words() - 2;
     Sm.lds_words = (int32_t)(pl.lds_bytes / 4);
-    Sm.gbits = gb + (size_t)pl.g_big * pl.gbits_words;
+    Sm.gbits = gb;
+    if (pl.g_big > 0) Sm.gbits_words = 0;  // (small-bin items keep their scan state in LDS)
     hipStream_t ss = pl.g_big > 0 ? w.s2 : s;
     if (pl.g_big > 0) HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
     if (t) HIP_TRY(hipEventRecord(w.lev[L][2], ss));
@@ -669,6 +718,8 @@ ItemArgs base_args(Workspace &w, const wcc_params &p, int32_t item_cap) {
   A.s_pre = p.s_pre;
   A.s_post = p.s_post;
   A.mode = p.prune_mode;
+  A.leaf_batch = p.prune_mode == WCC_PRUNE_PAPER && wcc_k_of(p.criterion, (int64_t)p.s_post + 1, p.lin_num,
+                                                              p.lin_den) >= 2;
   A.cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
   return A;
 }
@@ -748,7 +799,7 @@ GraphKey make_key(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const w
 int batched_sequence(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const ItemArgs &A,
                      const BatchPlan &pl, int32_t *out, bool timed, hipStream_t s) {
   int64_t N = g->num_vertices;
-  TRY(run_front(w, g, mem_in, false, false, false, s));
+  TRY(run_front(w, g, mem_in, false, false, s));
   TRY(prim_fill32(w.b[B_ACC].p, 0xffffffffu, N, s));
   TRY(prim_fill32(A.cnt, 0u, 2 * CNT_NUM, s));
   TRY(route_level0(w, A, pl, true, true, s));
@@ -857,7 +908,7 @@ int wcc_run_impl(Workspace &w, const wcc_csr *g, const int32_t *mem_in, const wc
 
   HIP_TRY(hipEventRecord(w.ev0, s));
   if (validate) TRY(run_validate(w, g, s));
-  TRY(run_front(w, g, mem_in, false, false, false, s));
+  TRY(run_front(w, g, mem_in, false, false, s));
   HIP_TRY(hipEventRecord(w.ev1, s));
   // (the counter block exists once run_front has sized the workspace)
   unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
@@ -934,7 +985,7 @@ int split_batch_impl(const wcc_csr *g, const int32_t *verts, const int64_t *set_
   HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (hb) return WCC_EINVAL;
-  TRY(run_front(w, g, mem, false, true, true, s));
+  TRY(run_front(w, g, mem, true, true, s));
   FrontCounts fc;
   TRY(read_counts(w, &fc, s));
   wcc_params p;
@@ -1100,7 +1151,7 @@ int ccr_impl(const wcc_csr *g, const int32_t *mem, int32_t *out, hipStream_t s) 
   Workspace *wp;
   TRY(get_ws(&wp));
   Workspace &w = *wp;
-  TRY(run_front(w, g, mem, false, false, false, s));
+  TRY(run_front(w, g, mem, false, false, s));
   TRY(items_ccr_init(mem, N, out, s));
   unsigned long long *cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
   TRY(prim_fill32(cnt, 0u, 2 * CNT_NUM, s));
@@ -1114,6 +1165,185 @@ int ccr_impl(const wcc_csr *g, const int32_t *mem, int32_t *out, hipStream_t s) 
   double ms = 0;
   TRY(run_levels(w, A, fc.nitems, p.criterion, p, &lv, &ms, &launches, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return WCC_OK;
+}
+
+// ---------------------------------------------------------------- Connectivity Modifier
+int bits_for(int64_t n) {
+  int b = 1;
+  while (b < 31 && (1LL << b) <= n) b++;
+  return b;
+}
+
+// The label-propagation CDA on the parts given by part_of (labels: global vertex ids of
+// the part's members): compaction of every part's induced subgraph, then `iters` rounds.
+int lp_impl(Workspace &w, const wcc_csr *g, const int32_t *part_of, int32_t iters, int32_t *comm, hipStream_t s) {
+  int64_t N = g->num_vertices;
+  TRY(run_front(w, g, part_of, false, false, s));
+  FrontCounts fc;
+  TRY(read_counts(w, &fc, s));
+  if (fc.na == 0) return WCC_OK;
+  int64_t E = fc.E > 0 ? fc.E : 1, na = fc.na;
+  for (int id : {B_LP_EROW, B_LP_ENB, B_LP_K1, B_LP_V1, B_LP_K2, B_LP_V2}) TRY(w.b[id].ensure((size_t)E * 4));
+  TRY(w.b[B_LP_LAB].ensure((size_t)na * 4));
+  TRY(w.b[B_LP_LAB2].ensure((size_t)na * 4));
+  TRY(w.b[B_LP_TMP].ensure(prim_radix_tmp_bytes(E)));
+  const FrontCounts *dfc = front_counts(w);
+  const int64_t *na_p = &dfc->na;
+  const int64_t *E_p = &dfc->E;
+  int32_t *lab = w.b[B_LP_LAB].as<int32_t>(), *lab2 = w.b[B_LP_LAB2].as<int32_t>();
+  TRY(lp_prepare(w.b[B_RS0].as<int64_t>(), w.b[B_RD0].as<int32_t>(), w.b[B_VTX0].as<int32_t>(),
+                 w.b[B_CIDV].as<int32_t>(), w.b[B_CLSTART].as<int64_t>(), w.b[B_ADJ0].as<int32_t>(), na_p, na,
+                 w.b[B_LP_EROW].as<int32_t>(), w.b[B_LP_ENB].as<int32_t>(), lab, s));
+  int bits = bits_for(N);
+  for (int t = 0; t < iters; t++) {
+    TRY(lp_round(w.b[B_RS0].as<int64_t>(), w.b[B_RD0].as<int32_t>(), w.b[B_LP_EROW].as<int32_t>(),
+                 w.b[B_LP_ENB].as<int32_t>(), na_p, na, E_p, fc.E, bits, lab, lab2, w.b[B_LP_K1].as<uint32_t>(),
+                 w.b[B_LP_V1].as<uint32_t>(), w.b[B_LP_K2].as<uint32_t>(), w.b[B_LP_V2].as<uint32_t>(),
+                 w.b[B_LP_TMP].p, w.b[B_LP_TMP].bytes, s));
+    int32_t *t2 = lab;
+    lab = lab2;
+    lab2 = t2;
+  }
+  return lp_out(w.b[B_VTX0].as<int32_t>(), lab, na_p, na, comm, s);
+}
+
+// The CDA step of Alg. 5 on every part at once: comm[v] = community of v (-1 outside the
+// parts).  *comm_bits receives the bit width of the labels.
+int cda_impl(Workspace &w, const wcc_csr *g, const int32_t *part_of, const wcc_cm_params &cm, int32_t *comm,
+             int *comm_bits, hipStream_t s) {
+  int64_t N = g->num_vertices;
+  TRY(prim_fill32(comm, 0xffffffffu, N, s));
+  *comm_bits = bits_for(N);
+  if (cm.cda == WCC_CDA_COMPONENTS) return ccr_impl(g, part_of, comm, s);
+  if (cm.cda == WCC_CDA_LABELPROP) return lp_impl(w, g, part_of, cm.cda_iters, comm, s);
+  // the caller's CDA: labels are any non-negative int32
+  *comm_bits = 31;
+  int rc = cm.fn(g, part_of, comm, cm.user, (void *)s);
+  if (rc != WCC_OK) return rc < 0 ? rc : WCC_EINVAL;
+  HIP_TRY(hipGetLastError());
+  return WCC_OK;
+}
+
+int check_cm(const wcc_cm_params *cm) {
+  if (!cm) return WCC_EINVAL;
+  if (cm->cda == WCC_CDA_COMPONENTS) return WCC_OK;
+  if (cm->cda == WCC_CDA_LABELPROP) return cm->cda_iters >= 0 && cm->cda_iters <= 1000 ? WCC_OK : WCC_EINVAL;
+  if (cm->cda == WCC_CDA_CALLBACK) return cm->fn ? WCC_OK : WCC_EINVAL;
+  return WCC_EINVAL;
+}
+
+// CM (Alg. 4) and its check CMC (Alg. 5), level by level: CCR, then per level one batched
+// canonical cut of every current set, split records, saved sets, the two parts of every
+// failing set, the CDA on all parts at once, and the next sets.
+int cm_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params &p, const wcc_cm_params &cm, int32_t *out,
+            wcc_stats *stats, wcc_record *rec, int64_t rec_cap, int64_t *nrec, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  TRY(check_params(p));
+  TRY(check_csr(g));
+  TRY(check_cm(&cm));
+  if (rec_cap < 0 || (rec_cap > 0 && !rec)) return WCC_EINVAL;
+  int64_t N = g->num_vertices;
+  wcc_stats st;
+  memset(&st, 0, sizeof(st));
+  if (nrec) *nrec = 0;
+  if (N == 0) {
+    if (stats) *stats = st;
+    return WCC_OK;
+  }
+  if (!mem_in || !out) return WCC_EINVAL;
+  Workspace *wp;
+  TRY(get_ws(&wp));
+  Workspace &w = *wp;
+  if (p.flags & WCC_FLAG_VALIDATE) TRY(run_validate(w, g, s));
+  size_t n4 = (size_t)N * 4;
+  for (int id : {B_CM_CUR, B_CM_PART, B_CM_COMM, B_CM_ACC, B_CM_SETOF, B_CM_VERTS, B_CM_SETIDX, B_CM_FLAG,
+                 B_CM_FSCAN, B_CM_K1, B_CM_V1, B_CM_K2, B_CM_V2, B_CM_NCOMM, B_CM_CAPS, B_CM_HASE, B_CM_SSZ,
+                 B_CM_LAM, B_CM_RUNF, B_CM_RUNS, B_CM_RUNSTART, B_CM_RUNSIZE})
+    TRY(w.b[id].ensure(n4));
+  TRY(w.b[B_CM_SO].ensure((size_t)(N + 1) * 8));
+  TRY(w.b[B_CM_SHASH].ensure((size_t)N * 8));
+  TRY(w.b[B_CM_PSZ].ensure(2 * n4));
+  TRY(w.b[B_CM_PMIN].ensure(2 * n4));
+  TRY(w.b[B_CM_SIDES].ensure((size_t)N + 64));
+  TRY(w.b[B_CM_CTL].ensure(64 * 8 + CNT_NUM * 8));
+  size_t tb = prim_radix_tmp_bytes(N), sb = prim_scan_tmp_bytes(N);
+  TRY(w.b[B_CM_TMP].ensure(tb > sb ? tb : sb));
+  int32_t *cur = w.b[B_CM_CUR].as<int32_t>(), *part = w.b[B_CM_PART].as<int32_t>();
+  int32_t *comm = w.b[B_CM_COMM].as<int32_t>(), *acc = w.b[B_CM_ACC].as<int32_t>();
+  int32_t *ctl = w.b[B_CM_CTL].as<int32_t>();  // [0] nv, [1] nsets, [2] nparts, [3] np, [4] nruns
+  unsigned long long *cnt = (unsigned long long *)(w.b[B_CM_CTL].as<unsigned long long>() + 64);
+  void *tmp = w.b[B_CM_TMP].p;
+  size_t tmpb = w.b[B_CM_TMP].bytes;
+  TRY(prim_fill32(cnt, 0u, 2 * CNT_NUM, s));
+  TRY(prim_fill32(acc, 0xffffffffu, N, s));
+  // Alg. 4: CCR, components larger than s_pre (a component is labelled by its smallest vertex)
+  TRY(ccr_impl(g, mem_in, comm, s));
+  TRY(cm_ccr_gate(comm, N, p.s_pre, w.b[B_CM_NCOMM].as<int32_t>(), cur, s));
+  int nbits = bits_for(N);
+  for (;;) {
+    TRY(prim_fill32(ctl, 0u, 8, s));
+    TRY(cm_set_keys(cur, N, w.b[B_CM_K1].as<uint32_t>(), w.b[B_CM_V1].as<uint32_t>(), ctl, s));
+    int32_t hv[2];
+    HIP_TRY(hipMemcpyAsync(hv, ctl, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t nv = hv[0];
+    if (nv == 0) break;
+    st.levels++;
+    int alt = 0;
+    TRY(prim_radix_sort_pairs(w.b[B_CM_K1].as<uint32_t>(), w.b[B_CM_V1].as<uint32_t>(), w.b[B_CM_K2].as<uint32_t>(),
+                              w.b[B_CM_V2].as<uint32_t>(), N, nbits, tmp, tmpb, s, &alt));
+    const uint32_t *sk = w.b[alt ? B_CM_K2 : B_CM_K1].as<uint32_t>();
+    const uint32_t *sv = w.b[alt ? B_CM_V2 : B_CM_V1].as<uint32_t>();
+    int32_t *verts = w.b[B_CM_VERTS].as<int32_t>(), *setidx = w.b[B_CM_SETIDX].as<int32_t>();
+    int64_t *so = w.b[B_CM_SO].as<int64_t>();
+    TRY(prim_fill32(w.b[B_CM_SETOF].p, 0xffffffffu, N, s));  // (vertices in no set: -1)
+    TRY(cm_sets(sk, sv, nv, ctl, w.b[B_CM_FLAG].as<int32_t>(), w.b[B_CM_FSCAN].as<int32_t>(), ctl + 1, so, verts,
+                setidx, w.b[B_CM_SETOF].as<int32_t>(), tmp, tmpb, s));
+    HIP_TRY(hipMemcpyAsync(hv, ctl, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t nsets = hv[1];
+    int32_t *caps = w.b[B_CM_CAPS].as<int32_t>(), *hase = w.b[B_CM_HASE].as<int32_t>();
+    int32_t *ssz = w.b[B_CM_SSZ].as<int32_t>(), *lam = w.b[B_CM_LAM].as<int32_t>();
+    int32_t *psz = w.b[B_CM_PSZ].as<int32_t>(), *pmin = w.b[B_CM_PMIN].as<int32_t>();
+    unsigned long long *shash = w.b[B_CM_SHASH].as<unsigned long long>();
+    uint8_t *sides = w.b[B_CM_SIDES].as<uint8_t>();
+    TRY(cm_caps(so, ctl + 1, nsets, p, caps, hase, ssz, shash, psz, pmin, s));
+    TRY(cm_edges(g, verts, setidx, w.b[B_CM_SETOF].as<int32_t>(), ctl, nv, hase, s));
+    // GetMinCut + MinCutPartition of every set (capped at k(n), Alg. 5)
+    TRY(split_batch_impl(g, verts, so, nsets, caps, lam, sides, nv, s));
+    TRY(prim_fill32(part, 0xffffffffu, N, s));
+    TRY(cm_outcome(so, verts, setidx, sides, ctl, ctl + 1, nv > nsets ? nv : nsets, hase, caps, lam, ssz, shash,
+                   psz, pmin, p.s_post, acc, part, ctl + 2, rec, rec_cap, cnt, s));
+    // the parts' communities (GetCommunities with the CDA), then the next sets
+    int comm_bits = nbits;
+    TRY(cda_impl(w, g, part, cm, comm, &comm_bits, s));
+    TRY(cm_part_count(part, N, w.b[B_CM_FLAG].as<int32_t>(), w.b[B_CM_FSCAN].as<int32_t>(), ctl + 3, tmp, tmpb, s));
+    int32_t hc[4];
+    HIP_TRY(hipMemcpyAsync(hc, ctl, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t np = hc[3];
+    TRY(prim_fill32(cur, 0xffffffffu, N, s));
+    if (np == 0) continue;
+    TRY(prim_fill32(w.b[B_CM_NCOMM].p, 0u, N, s));
+    TRY(prim_fill32(w.b[B_CM_RUNSIZE].p, 0u, np, s));
+    TRY(cm_next(part, comm, N, p.s_post, comm_bits, cur, w.b[B_CM_FSCAN].as<int32_t>(), ctl + 3, np,
+                w.b[B_CM_K1].as<uint32_t>(), w.b[B_CM_V1].as<uint32_t>(), w.b[B_CM_K2].as<uint32_t>(),
+                w.b[B_CM_V2].as<uint32_t>(), w.b[B_CM_NCOMM].as<int32_t>(), w.b[B_CM_RUNF].as<int32_t>(),
+                w.b[B_CM_RUNS].as<int32_t>(), w.b[B_CM_RUNSTART].as<int32_t>(), w.b[B_CM_RUNSIZE].as<int32_t>(),
+                ctl + 4, tmp, tmpb, s));
+  }
+  TRY(items_relabel(acc, N, w.b[B_MARK].as<int32_t>(), w.b[B_RANK].as<int32_t>(), out, w.b[B_TMP].p,
+                    w.b[B_TMP].bytes, s));
+  unsigned long long hcnt[CNT_NUM];
+  HIP_TRY(hipMemcpyAsync(hcnt, cnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  st.mincuts = (int64_t)hcnt[CNT_MINCUTS];
+  st.items = st.mincuts;
+  st.accepted = (int64_t)hcnt[CNT_ACCEPTED];
+  if (nrec) *nrec = (int64_t)hcnt[CNT_RECORDS];
+  st.ms_total = ms_since(t0);
+  if (stats) *stats = st;
   return WCC_OK;
 }
 
@@ -1302,6 +1532,42 @@ int wcc_ccr_components(const wcc_csr *g, const int32_t *membership_in, int32_t *
   }
 }
 
+int wcc_cm_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, const wcc_cm_params *cm,
+               int32_t *membership_out, wcc_stats *stats, wcc_record *records, int64_t records_cap,
+               int64_t *num_records, void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    wcc_params pp;
+    if (p) pp = *p;
+    else wcc_default_params(&pp);
+    if (!cm) return WCC_EINVAL;
+    return cm_impl(g, membership_in, pp, *cm, membership_out, stats, records, records_cap, num_records,
+                   (hipStream_t)stream);
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int wcc_cda(const wcc_csr *g, const int32_t *part_of, const wcc_cm_params *cm, int32_t *comm_out, void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    TRY(check_csr(g));
+    TRY(check_cm(cm));
+    if (cm->cda == WCC_CDA_CALLBACK) return WCC_EINVAL;
+    if (g->num_vertices == 0) return WCC_OK;
+    if (!part_of || !comm_out) return WCC_EINVAL;
+    Workspace *wp;
+    TRY(get_ws(&wp));
+    int bits = 0;
+    hipStream_t s = (hipStream_t)stream;
+    TRY(cda_impl(*wp, g, part_of, *cm, comm_out, &bits, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return WCC_OK;
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
 int wcc_mincut_split(const wcc_csr *g, const int32_t *verts, int32_t n, int32_t cap, int32_t *lambda,
                      uint8_t *side, void *stream) {
   if (!lambda || n < 0 || cap < 1) return WCC_EINVAL;
@@ -1347,7 +1613,7 @@ int wcc_cluster_csr(const wcc_csr *g, const int32_t *membership_in, int64_t *ncl
     Workspace *wp;
     TRY(get_ws(&wp));
     Workspace &w = *wp;
-    TRY(run_front(w, g, membership_in, false, true, false, s));
+    TRY(run_front(w, g, membership_in, true, false, s));
     FrontCounts fo;
     TRY(read_counts(w, &fo, s));
     *nclusters = fo.K;

@@ -51,6 +51,32 @@ __host__ __device__ inline int64_t wcc_k_of(int32_t crit, int64_t n, int32_t num
   return ((int64_t)num * n) / den + 1;
 }
 
+// ---------------------------------------------------------------- scan-state geometry
+// A cut capped at `cap` keeps its keys below bound + 1 levels, bound = min(cap, delta), and
+// the minimum degree delta of an item with n vertices and m list entries is at most m / n
+// (and n - 1).  The scan holds one bitmap per key level: a bit per vertex (nw0 64-bit
+// words) plus two summary levels (nw1, nw2 words).
+__host__ __device__ inline int64_t item_levels(int64_t n, int64_t m, int64_t cap) {
+  if (n < 2) return 2;
+  int64_t d = m / n;
+  if (d > n - 1) d = n - 1;
+  int64_t b = cap < d ? cap : d;
+  return (b < 1 ? 1 : b) + 1;
+}
+__host__ __device__ inline int64_t item_level_words(int64_t n) {
+  int64_t nw0 = (n + 63) / 64, nw1 = (nw0 + 63) / 64, nw2 = (nw1 + 63) / 64;
+  return nw0 + nw1 + nw2;
+}
+// 64-bit bitmap words of the scan (all levels)
+__host__ __device__ inline int64_t item_bitmap_words(int64_t n, int64_t m, int64_t cap) {
+  return item_levels(n, m, cap) * item_level_words(n);
+}
+// 32-bit LDS words of the scan state kept in LDS: the bitmaps and five words per vertex
+// (keys, union-find, list lengths, list starts, row starts)
+__host__ __device__ inline int64_t item_state_words(int64_t n, int64_t m, int64_t cap) {
+  return 2 * item_bitmap_words(n, m, cap) + 5 * n;
+}
+
 // ---------------------------------------------------------------- item descriptors
 // A queued vertex set ("item") lives in one of two arenas (depth & 1): positions
 // [b, b+n) hold its vertices in ascending global id (local id = position - b), and its
@@ -118,16 +144,19 @@ struct ItemArgs {
   const int32_t *split_cap;         // per set
   const int64_t *split_pos;         // per set: offset of its first vertex in the caller's order
   // device-driven levels (batched form): the item count of the launch is read on the
-  // device, and children larger than small_max go to a second list
+  // device, and children whose scan state exceeds small_words go to a second list
   const int32_t *nitems_dev;        // when set, the launch's item count (overrides nitems),
                                     // clamped to nitems (the list's capacity)
-  ItemDesc *out_big;                // children with n > small_max (nullptr: all go to out)
+  ItemDesc *out_big;                // children with a larger state (nullptr: all go to out)
   int32_t *out_big_count;
   int32_t out_big_cap;
-  int32_t small_max;
+  int64_t small_words;              // LDS words of a small-bin workgroup
   // CCR only: each vertex of a processed cluster gets the smallest global id of its
   // component inside the cluster's induced subgraph (no cut, no children)
   int32_t *ccr_out;
+  // PAPER mode: items with a vertex of degree 1 are peeled to their 2-core in one batch
+  // (every step of the one-at-a-time peel fails its cut: k(s_post + 1) >= 2)
+  int32_t leaf_batch;
 };
 
 // ---------------------------------------------------------------- device helpers

@@ -98,6 +98,43 @@ __global__ void __launch_bounds__(FB) k_validate_entries(const OT *off, const in
   if (h) atomicAdd(&bad[2], h);
 }
 
+// bad[3]: entries whose neighbour id already occurs earlier in the same row (parallel
+// edges).  Row v owns the open-addressing table slots [2*off[v], 2*off[v+1]) (twice its
+// length, so linear probing always finds a free slot), split over two scratch arrays of
+// nnz words each (tabA: slots below nnz, tabB: the rest), filled with -1 beforehand.  An
+// insertion that meets its own id counts one duplicate; exact for any row length.
+template <typename OT>
+__global__ void __launch_bounds__(FB) k_validate_dups(const OT *off, const int32_t *idx, int64_t N, int64_t nnz,
+                                                      int32_t *tabA, int32_t *tabB, unsigned long long *bad) {
+  __shared__ int64_t sh_r[2];
+  __shared__ int64_t cache[FROWS];
+  int64_t e0 = (int64_t)blockIdx.x * FTILE, e1 = e0 + FTILE < nnz ? e0 + FTILE : nnz;
+  bool cached = tile_rows(off, N, e0, e1, sh_r, cache);
+  int64_t r0 = sh_r[0], r1 = sh_r[1];
+  unsigned long long nd = 0;
+  for (int i = 0; i < FITEMS; i++) {
+    int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
+    if (e >= e1) break;
+    int64_t v = cached ? r0 + row_in_cache(cache, r1 - r0 + 2, e) : row_of(off, r0, r1, e);
+    int64_t b = (int64_t)off[v], len = (int64_t)off[v + 1] - b;
+    int32_t u = idx[e];
+    int64_t size = 2 * len, base = 2 * b;
+    int64_t h = (int64_t)(pair_mix((uint64_t)(uint32_t)u, 0x5bd1e995ull) % (uint64_t)size);
+    for (int64_t t = 0; t < size; t++) {
+      int64_t slot = base + h;
+      int32_t *p = slot < nnz ? &tabA[slot] : &tabB[slot - nnz];
+      int32_t old = atomicCAS(p, -1, u);
+      if (old == -1) break;
+      if (old == u) {
+        nd++;
+        break;
+      }
+      h = h + 1 == size ? 0 : h + 1;
+    }
+  }
+  if (nd) atomicAdd(&bad[3], nd);
+}
+
 // ---------------------------------------------------------------- grouping
 // Every size the front end produces (assigned vertices na, clusters K, intra entries E,
 // initial items) stays in device counters (FrontCounts), so the whole front end runs
@@ -340,8 +377,23 @@ int front_validate(const FrontBufs &f, hipStream_t s, int *ok) {
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(h, f.dcnt, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    // parallel edges: only once ids and offsets are known to be valid
+    if (h[1] == 0 && h[2] == 0) {
+      int rc = prim_fill32(f.vtab_a, 0xffffffffu, f.nnz, s);
+      if (!rc) rc = prim_fill32(f.vtab_b, 0xffffffffu, f.nnz, s);
+      if (rc) return rc;
+      if (f.obits == 32)
+        hipLaunchKernelGGL(k_validate_dups<int32_t>, dim3(ge), dim3(FB), 0, s, (const int32_t *)f.off, f.idx, f.N,
+                           f.nnz, f.vtab_a, f.vtab_b, f.dcnt);
+      else
+        hipLaunchKernelGGL(k_validate_dups<int64_t>, dim3(ge), dim3(FB), 0, s, (const int64_t *)f.off, f.idx, f.N,
+                           f.nnz, f.vtab_a, f.vtab_b, f.dcnt);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(h, f.dcnt, sizeof(h), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
   }
-  *ok = (h[1] == 0 && h[2] == 0);
+  *ok = (h[1] == 0 && h[2] == 0 && h[3] == 0);
   return WCC_OK;
 }
 

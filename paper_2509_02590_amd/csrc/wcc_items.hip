@@ -33,6 +33,11 @@
 
 #include "wcc_internal.h"
 
+// The phases below are compiled as separate functions (not inlined into the three
+// placements of process_item_t): one copy each keeps the code object small and the build
+// fast, and a phase's registers are not live across the others.
+#define NOINL __device__ __attribute__((noinline))
+
 namespace {
 
 // threads per item workgroup: 256, or 512 for launches with one workgroup per CU (more
@@ -41,7 +46,6 @@ constexpr int IB_SMALL = 256;
 constexpr int IB_MAX = 512;
 constexpr int NW_MAX = IB_MAX / 64;
 DEV int ib() { return (int)blockDim.x; }
-constexpr int MAX_LEVEL = 62;
 constexpr int CH = 16;   // entries per thread per chunk in entry-parallel passes
 
 struct Sh {
@@ -386,7 +390,8 @@ DEV void err(const ItemArgs &A, int code) {
 // one tree; c = the root with the most members.  Then every edge is united from the side
 // of an endpoint that is not (yet) a child of c; an edge skipped from both sides joins two
 // members of c's tree, so the components are exact.  Rows of c's members are not read.
-DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
+NOINL int item_cc(const St &s_in, bool use_deg, int kmin, Sh &sh) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
   int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += ib()) {
@@ -455,7 +460,8 @@ DEV int item_cc(const St &s, bool use_deg, int kmin, Sh &sh) {
 // are compacted into the other arena inside [b, b+n) / [eb, eb+m) and pushed.
 // Uses A (sizes), D (child starts), E (new positions), C (row offsets by new position)
 // and F (write cursors by new position).
-DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gate, Sh &sh) {
+NOINL void item_rebuild(const ItemArgs &A, const St &s_in, const ItemDesc &d, int gate, Sh &sh) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
   const Arena &ar = A.ar[d.depth & 1];
   const Arena &nx = A.ar[(d.depth + 1) & 1];
   int n = s.n;
@@ -575,7 +581,8 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
     if (ldr(&s.B[i]) != i) continue;
     ItemDesc c = child(i);
     atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * c.n + 4LL * c.m));
-    if (A.out_big && c.n > A.small_max) {
+    int ccap = (int)wcc_k_of(A.crit, c.n, A.lin_num, A.lin_den);
+    if (A.out_big && item_state_words(c.n, c.m, ccap) > A.small_words) {
       int slot = atomicAdd(A.out_big_count, 1);
       if (slot < A.out_big_cap) A.out_big[slot] = c;
       else err(A, WCC_ENOMEM);
@@ -588,10 +595,167 @@ DEV void item_rebuild(const ItemArgs &A, const St &s, const ItemDesc &d, int gat
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- PAPER-mode leaf peel
+// An item (connected, n vertices) whose minimum degree is 1 has canonical cut 1 with
+// S = {its smallest vertex of degree 1} (Phase 0 stops at bound 1).  When every size on
+// the way fails its cut (k >= 2), WCC as printed therefore removes, one item at a time,
+// the smallest vertex of degree 1 and continues with the rest, until no vertex of degree
+// 1 is left (the 2-core) or the rest has s_post vertices or fewer.  This computes that
+// whole sequence at once, with one split record per removal:
+//   * synchronous peel rounds of the vertices of degree <= 1 (the hanging trees); round(u)
+//     is the height of u's hanging subtree, and M(u) = the largest id in that subtree;
+//     a tree is rooted at its largest id, which is never removed;
+//   * the one-at-a-time order is the sort by (M(u), round(u)): the smallest leaf goes
+//     first, and a subtree is consumed in the order its largest id allows;
+//   * a counting sort by M that places the rounds in order (inside one round the M
+//     values differ: equal M means one vertex is the other's ancestor).
+// Arrays: A degrees then the removal order, B round (-1 never removed), C M, D the rounds'
+// vertices in round order then the suffix minima of the order, E round starts, F bucket
+// starts.  Writes the records; returns the number of vertices left when the rest goes on
+// (the 2-core, B[i] = its smallest vertex for members, -1 otherwise) or 0.
+DEV int block_suffix_min(int v, int carry, Sh &sh, int *chunk_min) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6, NW = (int)(blockDim.x >> 6);
+  int x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_down(x, d, 64);
+    if (lane + d < 64) x = y < x ? y : x;
+  }
+  if (lane == 0) sh.red[w] = x;
+  __syncthreads();
+  int later = carry, all = carry;
+  for (int j = 0; j < NW; j++) {
+    int r = sh.red[j];
+    if (j > w) later = r < later ? r : later;
+    all = r < all ? r : all;
+  }
+  __syncthreads();
+  *chunk_min = all;
+  return x < later ? x : later;
+}
+
+NOINL int item_leaf_peel(const ItemArgs &A, const St &s_in, const ItemDesc &d, Sh &sh) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
+  const Arena &ar = A.ar[d.depth & 1];
+  const int n = s.n;
+  // a tree keeps its largest vertex (it is the last one standing)
+  const int pin = (long long)s.m == 2LL * (n - 1) ? n - 1 : -1;
+  if (threadIdx.x == 0) sh.vi[0] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += ib()) {
+    int dg = row_end(s, i) - ldr(&s.R[i]);
+    st(&s.A[i], dg);
+    bool leaf = dg <= 1 && i != pin;
+    st(&s.B[i], leaf ? 0 : -1);
+    if (leaf) st(&s.D[atomicAdd(&sh.vi[0], 1)], i);
+  }
+  __syncthreads();
+  int head = 0, tail = sh.vi[0], r = 0;
+  while (head < tail) {
+    if (threadIdx.x == 0) {
+      st(&s.E[r], head);
+      sh.vi[1] = tail;
+    }
+    __syncthreads();
+    for (int f = head + (int)threadIdx.x; f < tail; f += ib()) {
+      int u = ld(&s.D[f]);
+      int mu = u;
+      for (int e = ldr(&s.R[u]), e1 = row_end(s, u); e < e1; e++) {
+        int j = adj_at(s, e);
+        int bj = ld(&s.B[j]);
+        if (bj >= 0 && bj < r) {  // a child: removed in an earlier round
+          int mj = ld(&s.C[j]);
+          mu = mj > mu ? mj : mu;
+        } else if (bj < 0 || bj > r) {  // alive: one neighbour fewer
+          int old = atomicSub(&s.A[j], 1);
+          if (old == 2 && j != pin) {
+            st(&s.B[j], r + 1);
+            st(&s.D[atomicAdd(&sh.vi[1], 1)], j);
+          }
+        }
+      }
+      st(&s.C[u], mu);
+    }
+    __syncthreads();
+    head = tail;
+    tail = sh.vi[1];
+    r++;
+    __syncthreads();
+  }
+  const int P = tail, R = r;
+  if (threadIdx.x == 0) st(&s.E[R], P);
+  // bucket sizes by M, then bucket starts (exclusive scan over m)
+  for (int i = threadIdx.x; i < n; i += ib()) st(&s.F[i], 0);
+  __syncthreads();
+  for (int f = threadIdx.x; f < P; f += ib()) atomicAdd(&s.F[ld(&s.C[ld(&s.D[f])])], 1);
+  __syncthreads();
+  int carry = 0;
+  for (int base = 0; base < n; base += ib()) {
+    int i = base + threadIdx.x;
+    int v = i < n ? ld(&s.F[i]) : 0;
+    int tot;
+    int pre = block_excl_scan<IB_MAX>(v, sh.red, &tot);
+    if (i < n) st(&s.F[i], carry + pre);
+    carry += tot;
+  }
+  __syncthreads();
+  // removal order, round by round (A = order; the degrees are no longer needed)
+  for (int q = 0; q < R; q++) {
+    int f0 = ld(&s.E[q]), f1 = ld(&s.E[q + 1]);
+    for (int f = f0 + (int)threadIdx.x; f < f1; f += ib()) {
+      int u = ld(&s.D[f]);
+      st(&s.A[atomicAdd(&s.F[ld(&s.C[u])], 1)], u);
+    }
+    __syncthreads();
+  }
+  // smallest vertex that is never removed, then suffix minima of the order (into D)
+  int cm = 0x7fffffff;
+  for (int i = threadIdx.x; i < n; i += ib())
+    if (ld(&s.B[i]) < 0) cm = i < cm ? i : cm;
+  cm = (int)block_min_u64<IB_MAX>((unsigned long long)(uint32_t)cm, sh.redu);
+  int run = cm;
+  for (int top = ((P + ib() - 1) / ib()) * ib(); top > 0; top -= ib()) {
+    int i = top - ib() + threadIdx.x;
+    int v = i < P ? ld(&s.A[i]) : 0x7fffffff;
+    int cmin;
+    int suf = block_suffix_min(v, run, sh, &cmin);
+    if (i < P) st(&s.D[i], suf);
+    run = cmin;
+  }
+  __syncthreads();
+  // steps taken: while the current set is larger than s_post and has a vertex of degree 1
+  const int steps = P < n - A.s_post ? P : n - A.s_post;
+  for (int i = threadIdx.x; i < steps; i += ib()) {
+    int ni = n - i;
+    wcc_record rc;
+    rc.minv = ar.vtx[d.b + ld(&s.D[i])];
+    rc.n = ni;
+    rc.k = (int)wcc_k_of(A.crit, ni, A.lin_num, A.lin_den);
+    rc.lambda = 1;
+    rc.ssize = 1;
+    rc.reserved = 0;
+    rc.shash = vhash(ar.vtx[d.b + ld(&s.A[i])]);
+    if (A.rec) {
+      unsigned long long q = atomicAdd(&A.cnt[CNT_RECORDS], 1ull);
+      if ((long long)q < A.rec_cap) A.rec[q] = rc;
+    }
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&A.cnt[CNT_MINCUTS], (unsigned long long)steps);
+    if (steps > 1) atomicAdd(&A.cnt[CNT_ITEMS], (unsigned long long)(steps - 1));
+  }
+  __syncthreads();
+  if (steps < P || n - P <= A.s_post) return 0;  // the rest has at most s_post vertices
+  for (int i = threadIdx.x; i < n; i += ib()) st(&s.B[i], ld(&s.B[i]) < 0 ? cm : -1);
+  __syncthreads();
+  return n - P;
+}
+
 // ---------------------------------------------------------------- k-core peel
 // A[i] ends as i's degree inside the surviving core (alive iff A[i] >= k).
 // Returns the number of removed vertices.  D and E hold the frontiers.
-DEV int item_peel(const St &s, int k, Sh &sh) {
+NOINL int item_peel(const St &s_in, int k, Sh &sh) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
   int n = s.n;
   if (threadIdx.x == 0) sh.vi[0] = 0;
   __syncthreads();
@@ -679,7 +843,8 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
   const int n = __builtin_amdgcn_readfirstlane(s.n);
   const unsigned ls = (unsigned)__builtin_amdgcn_readfirstlane(s.ls);
   bound = __builtin_amdgcn_readfirstlane(bound);
-  const unsigned my_lv = __umul24((unsigned)(lane <= bound ? lane : bound), ls);
+  // (lane's own level; used only for levels up to the bound)
+  const unsigned my_lv = __umul24((unsigned)lane, ls);
   int steps = 0;
   int x = -1, jx = 0;      // next vertex when already known, and its level
   bool have = false;       // x's list (start e0, length cnt, first 64 entries y) is loaded
@@ -717,11 +882,14 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       ce0 = ldr(&stv[cand]);
       ccnt = ldr(&lenv[cand]);
     }
-    // x leaves levels 0..jx (lanes at or below jx; one of them marks it scanned)
+    // x leaves levels 0..jx (lane l clears level l, and l + 64, ... above 63; one of them
+    // marks it scanned)
     if (lane <= jx) {
       atomicAnd((unsigned long long *)&s.bits[my_lv + xw], ~xbit);
       st(&s.A[x], SCANNED);
     }
+    for (int lb = 64; lb <= jx; lb += 64)
+      if (lb + lane <= jx) atomicAnd((unsigned long long *)&s.bits[__umul24((unsigned)(lb + lane), ls) + xw], ~xbit);
     // longer lists: the next 256 entries are loaded before the prefetch below, so that
     // waiting for them does not wait for it
     int yv[4];
@@ -756,12 +924,19 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     }
     // only keys raised to jx or above can decide the next vertex; when there are any, one
     // reduction of (level + 1, 2^24 - 1 - id) packed finds the highest raised level and,
-    // inside it, the smallest id (items have fewer than 2^24 vertices)
+    // inside it, the smallest id (items have fewer than 2^24 vertices; bounds above 126
+    // do not fit the packed level and take two reductions)
     int nx = cand;
     if (__ballot(bl >= jx)) {
-      int P = wave_max_i(bl >= jx ? ((bl + 1) << 24) | (0xFFFFFF - by) : 0);
-      int M = (P >> 24) - 1;
-      int pid = 0xFFFFFF - (P & 0xFFFFFF);
+      int M, pid;
+      if (bound < 127) {
+        int P = wave_max_i(bl >= jx ? ((bl + 1) << 24) | (0xFFFFFF - by) : 0);
+        M = (P >> 24) - 1;
+        pid = 0xFFFFFF - (P & 0xFFFFFF);
+      } else {
+        M = wave_max_i(bl >= jx ? bl : -1);
+        pid = wave_min_i(bl == M ? by : 0x7fffffff);
+      }
       if (M > jx) {
         nx = pid;
         jx = M;
@@ -787,7 +962,8 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
 // which most edges join one tree and stop at a single comparison.  Uses B (union-find) and the
 // entry marks (used edges); returns false as soon as a forest does not span (the greedy
 // choice can fail even when lambda >= t: the caller then runs the scans).
-DEV bool forest_certificate(const St &s, int t, Sh &sh) {
+NOINL bool forest_certificate(const St &s_in, int t, Sh &sh) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
   const int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
   mark_clear(s, s.m);
@@ -833,7 +1009,8 @@ DEV bool forest_certificate(const St &s, int t, Sh &sh) {
 // per forest, and then every unused edge joins the first forest whose trees it connects.
 // One pass over the edges instead of t, but no early stop when a forest cannot span.
 template <int TMAX>
-DEV bool forest_certificate_one(const St &s, int t, Sh &sh) {
+NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
   const int n = s.n;
   auto P = [&](int f) -> int32_t * {
     return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : f == 3 ? s.E : f == 4 ? s.C : s.F;
@@ -900,8 +1077,9 @@ DEV bool forest_certificate_one(const St &s, int t, Sh &sh) {
 
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
 template <bool LDS>
-DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, Sh &sh,
+NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int cap, Sh &sh,
                     long long *steps_out, long long *rounds_out) {
+  const St s = s_in;  // (a local copy: its fields stay in registers)
   int n = s.n;
   unsigned long long pt = s.pf ? wall_clock64() : 0;
   // Phase 0: minimum degree and its smallest vertex
@@ -916,10 +1094,6 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   int bound = delta < cap ? delta : cap;
   int s_kind = delta <= cap ? 1 : 0;  // 0 empty, 1 singleton dv, 2 set in F
   long long steps = 0, rounds = 0;
-  if (bound > 1 && bound > MAX_LEVEL) {
-    err(A, WCC_EUNSUPPORTED);
-    bound = 1;  // give up on this item; the error is reported
-  }
   // lambda >= bound: no super-vertex degree can fall below the bound, so the rounds would
   // end with (bound, the Phase-0 set); a certificate of it gives the same result at once
   // (bound spanning trees need bound * (n - 1) edges: sparser items skip the attempt)
@@ -928,7 +1102,7 @@ DEV int item_mincut(const ItemArgs &A, const St &s, const ItemDesc &d, int cap, 
   // checking every forest per edge, most of all when the union-finds are in global memory)
   constexpr int TONE = 4;
   if (bound > 1 && (long long)s.m / 2 >= (long long)bound * (n - 1) &&
-      (bound <= TONE ? forest_certificate_one<TONE>(s, bound, sh) : forest_certificate(s, bound, sh))) {
+      (bound <= TONE ? forest_certificate_one<TONE>(s_in, bound, sh) : forest_certificate(s_in, bound, sh))) {
     if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
     bound = -bound;  // (certified; restored below)
   }
@@ -1092,7 +1266,7 @@ struct Geo {
 };
 DEV Geo item_geo(int n, long long m, int cap) {
   Geo g;
-  g.lv = (cap < MAX_LEVEL ? cap : MAX_LEVEL) + 1;
+  g.lv = (int)item_levels(n, m, cap);
   g.nw0 = (n + 63) / 64;
   g.nw1 = (g.nw0 + 63) / 64;
   g.nw2 = (g.nw1 + 63) / 64;
@@ -1252,6 +1426,19 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     }
   } else if (d.m == 0) {
     return;  // Alg. 3 tests only sets with at least one edge
+  } else if (A.leaf_batch) {
+    // Phase 0's minimum degree: 1 means a run of single-vertex splits (peeled at once)
+    int dmin = 0x7fffffff;
+    for (int i = threadIdx.x; i < n; i += ib()) {
+      int dg = row_end(s, i) - ldr(&s.R[i]);
+      dmin = dg < dmin ? dg : dmin;
+    }
+    dmin = (int)block_min_u64<IB_MAX>((unsigned long long)(uint32_t)dmin, sh.redu);
+    if (dmin == 1) {
+      if (item_leaf_peel(A, s, d, sh) > 0) item_rebuild(A, s, d, A.s_post, sh);
+      ph_mark(A, s, 9, &pt);
+      return;
+    }
   }
   int lam = item_mincut<LDS>(A, s, d, k, sh, &steps, &rounds);
   pt = s.pf ? wall_clock64() : 0;
@@ -1392,14 +1579,24 @@ __global__ void k_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *
 }
 
 // ---------------------------------------------------------------- item ordering
-// keys for a descending-size sort (largest items first); counts items above small_max
-__global__ void k_item_keys(const ItemDesc *items, int32_t n, uint32_t *keys, uint32_t *vals, int small_max,
-                            int32_t *nbig) {
+// Keys of a sort by descending scan-state size (largest items first); sz[0] counts the
+// items whose state exceeds the small-bin LDS, sz[1..2] (64-bit) receives the largest
+// bitmap a global-state item of this list or of its descendants can need.  The cut cap of
+// an item is k(n) (descendants: at most k(n), monotone in n), or the caller's cap of its set.
+__global__ void k_item_keys(const ItemDesc *items, int32_t n, uint32_t *keys, uint32_t *vals, SortNeed nd,
+                            int32_t *sz) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  keys[i] = 0x7fffffffu - (uint32_t)items[i].n;
+  ItemDesc d = items[i];
+  int64_t cap = nd.caps ? nd.caps[nd.set[i]] : wcc_k_of(nd.crit, d.n, nd.lin_num, nd.lin_den);
+  int64_t need = item_state_words(d.n, d.m, cap);
+  keys[i] = 0x7fffffffu - (uint32_t)(need < 0x7ffffffe ? need : 0x7ffffffe);
   vals[i] = (uint32_t)i;
-  if (items[i].n > small_max) atomicAdd(nbig, 1);
+  if (need > nd.small_words) atomicAdd(&sz[0], 1);
+  // (the list-entry bound of a descendant is unknown: every vertex pair)
+  int64_t bits = nd.caps ? item_bitmap_words(d.n, d.m, cap)
+                         : item_bitmap_words(d.n, (int64_t)d.n * (d.n - 1), cap);
+  atomicMax((unsigned long long *)(sz + 2), (unsigned long long)bits);
 }
 // Keys of a largest-first sort of a list whose length is read on the device: entries
 // past the count get the largest key and sort last.
@@ -1443,22 +1640,6 @@ __global__ void k_relabel(const int32_t *acc, const int32_t *rank, int64_t N, in
 }  // namespace
 
 int items_block() { return IB_SMALL; }
-
-// LDS words a workgroup needs to keep an item's scan arrays of n vertices (cut cap `cap`)
-// in LDS (the 16-bit adjacency copy is optional on top of this)
-int64_t items_lds_words(int64_t n, int cap) {
-  int64_t nw0 = (n + 63) / 64, nw1 = (nw0 + 63) / 64, nw2 = (nw1 + 63) / 64;
-  int lv = (cap < MAX_LEVEL ? cap : MAX_LEVEL) + 1;
-  return 5 * n + 2 * (int64_t)lv * (nw0 + nw1 + nw2);
-}
-int items_max_level() { return MAX_LEVEL; }
-
-// words of 64-bit bitmap storage one workgroup needs for an item of n vertices
-int64_t items_bitmap_words(int64_t n, int cap) {
-  int64_t nw0 = (n + 63) / 64, nw1 = (nw0 + 63) / 64, nw2 = (nw1 + 63) / 64;
-  int lv = (cap < MAX_LEVEL ? cap : MAX_LEVEL) + 1;
-  return (int64_t)lv * (nw0 + nw1 + nw2);
-}
 
 int items_launch(const ItemArgs &A, int grid, size_t lds_bytes, hipStream_t s) {
   if (grid <= 0 || (!A.nitems_dev && A.nitems <= 0)) return WCC_OK;
@@ -1507,11 +1688,13 @@ int items_route0(const ItemDesc *sorted, int32_t nitems, const int32_t *nbig, co
 
 int items_sort_desc(const ItemDesc *in, int32_t n, ItemDesc *out, const int32_t *set_in, int32_t *set_out,
                     uint32_t *k1, uint32_t *v1, uint32_t *k2, uint32_t *v2, void *tmp, size_t tmp_bytes,
-                    hipStream_t s, int small_max, int32_t *nbig) {
+                    hipStream_t s, const SortNeed &nd, int32_t *sz) {
   if (n <= 0) return WCC_OK;
-  int rc0 = prim_fill32(nbig, 0u, 1, s);
+  int rc0 = prim_fill32(sz, 0u, 4, s);
   if (rc0) return rc0;
-  hipLaunchKernelGGL(k_item_keys, dim3((n + 255) / 256), dim3(256), 0, s, in, n, k1, v1, small_max, nbig);
+  SortNeed nd2 = nd;
+  nd2.set = set_in;
+  hipLaunchKernelGGL(k_item_keys, dim3((n + 255) / 256), dim3(256), 0, s, in, n, k1, v1, nd2, sz);
   HIP_TRY(hipGetLastError());
   int bits = 31, alt = 0;
   int rc = prim_radix_sort_pairs(k1, v1, k2, v2, n, bits, tmp, tmp_bytes, s, &alt);

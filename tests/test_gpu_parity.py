@@ -296,3 +296,70 @@ def test_ccr_components_match_oracle():
     for off, adj, memb in cases:
         got = w.ccr_components(_t(off, np.int32), _t(adj, np.int32), _t(memb, np.int32)).cpu().numpy()
         assert np.array_equal(got, _ccr_expected(off, adj, memb))
+
+
+def _hanging_trees_graph(rng, n_core, n_tree_vertices, clusters=3):
+    """Clusters made of a dense-enough core (a cycle with chords) plus hanging trees of
+    every shape (paths, stars, random trees) attached to core vertices, a few pure trees
+    and a long pendant path: every PAPER-mode item starts with vertices of degree 1."""
+    edges, memb, base = [], [], 0
+    for c in range(clusters):
+        core = list(range(base, base + n_core))
+        edges += [(core[i], core[(i + 1) % n_core]) for i in range(n_core)]
+        edges += [(core[i], core[(i + 7) % n_core]) for i in range(0, n_core, 3)]
+        nxt = base + n_core
+        verts = list(core)
+        while nxt < base + n_core + n_tree_vertices:
+            kind = int(rng.integers(0, 3))
+            size = int(rng.integers(1, 12))
+            root = int(rng.choice(verts))
+            new = list(range(nxt, nxt + size))
+            if kind == 0:    # a path
+                chain = [root] + new
+                edges += list(zip(chain[:-1], chain[1:]))
+            elif kind == 1:  # a star
+                edges += [(root, new[0])] + [(new[0], x) for x in new[1:]]
+            else:            # a random tree
+                pool = [root]
+                for x in new:
+                    edges.append((int(rng.choice(pool)), x))
+                    pool.append(x)
+            verts += new
+            nxt += size
+        memb += [c] * (nxt - base)
+        base = nxt
+    # a pure tree cluster and a core with one long pendant path
+    tree = [(base + i, base + int(rng.integers(0, i))) for i in range(1, 40)]
+    edges += tree
+    memb += [clusters] * 40
+    base += 40
+    edges += [(base + i, base + (i + 1) % 12) for i in range(12)] + [(base + 11 + i, base + 12 + i) for i in range(300)]
+    memb += [clusters + 1] * 312
+    base += 312
+    # a shuffled labelling so that ids do not follow the tree structure
+    perm = rng.permutation(base)
+    edges = [(int(perm[a]), int(perm[b])) for a, b in edges]
+    memb_p = np.empty(base, np.int32)
+    memb_p[perm] = np.array(memb, np.int32)
+    off, adj = csr_from_edges(base, edges)
+    return off, adj, memb_p
+
+
+@pytest.mark.parametrize("crit", ["log10", "log2"])
+def test_paper_leaf_runs(crit):
+    """PAPER mode on items with hanging trees: the removal of vertices of degree 1 one at a
+    time (each a split record) is computed by the GPU in one batch whenever every step
+    fails its cut, and by single steps otherwise; both against the oracle."""
+    rng = np.random.default_rng(808 if crit == "log10" else 809)
+    for trial in range(3):
+        off, adj, memb = _hanging_trees_graph(rng, int(rng.integers(15, 60)), int(rng.integers(50, 400)))
+        for s in (1, 3, 9, 10, 25):
+            st = _compare(off, adj, memb, s_pre=s, s_post=s, mode="paper", criterion=crit)
+            assert st.mincuts > 0
+
+
+def test_wcc_c1_full_paper():
+    """The 1M-vertex / 20M-edge workload in PAPER mode (runs of single-vertex splits)."""
+    g = gen.c1()
+    st = _compare(g.offsets, g.indices, g.membership, mode="paper")
+    assert st.mincuts > 1000

@@ -1,12 +1,21 @@
-"""Parity at full size: the 10M-vertex / 200M-edge workload (clusters up to ~1e5 vertices,
-nested bridges) and, when WCC_TEST_C4=1, the 250M-vertex / 2B-edge workload (int64
-offsets, clusters up to ~1e6 vertices).  The oracle cannot cut their largest clusters in
-reasonable time, so it runs on a random sample of whole input clusters (WCC treats
-clusters independently) and is compared set by set; every output set of the full run,
-largest clusters included, is checked for the properties the method guarantees at any
-size.  The CM-style call (mincut_split_batch over every CCR component) is checked the
-same way on sampled sets."""
+"""Parity at full size, against the oracle:
+
+* the whole 10M-vertex / 200M-edge workload (clusters up to ~1e5 vertices, bridges nested
+  up to three levels deep): every vertex's label and every split record (minv, n, k,
+  lambda, |S|, hash of S), in both execution forms;
+* clusters of 20k-60k vertices with nested bridges, in both pruning modes and under two
+  criteria, so that cut items above 16,384 vertices (summary level of the scan bitmaps)
+  and items whose scan state lives in global memory are compared record by record;
+* the 250M-vertex / 2B-edge workload (int64 offsets, clusters up to ~1e6 vertices): the
+  oracle on a sample of whole input clusters that includes the largest ones (WCC treats
+  clusters independently), compared label by label and record by record, and both
+  execution forms identical on every vertex.  It is skipped only when the host has too
+  little memory for the input and the oracle, with the measured amount in the reason.
+
+The CM-style call (mincut_split_batch over every CCR component) is checked against the
+oracle on sampled sets of the 10M workload."""
 import os
+import time
 
 import numpy as np
 import pytest
@@ -18,8 +27,7 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 torch = pytest.importorskip("torch")
 
-WORKLOADS = ["c2", pytest.param("c4", marks=pytest.mark.skipif(
-    os.environ.get("WCC_TEST_C4") != "1", reason="2B-edge workload: set WCC_TEST_C4=1 (needs ~60 GB host RAM)"))]
+C4_HOST_BYTES = 96 << 30   # CSR (18 GB) + generator peak + oracle working set, with margin
 
 
 def _dev():
@@ -28,13 +36,33 @@ def _dev():
     return torch.device("cuda:0")
 
 
+def _mem_available():
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemAvailable:"):
+                    return int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return 0
+
+
+def _threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return max(1, min(16, os.cpu_count() or 1))
+
+
 _CACHE = {}
 
 
 def _workload(name):
     if name not in _CACHE:
         _CACHE.clear()
-        g = gen.c2() if name == "c2" else gen.c4()
+        t0 = time.time()
+        g = {"c2": gen.c2, "c4": gen.c4}[name]()
+        print("%s generated in %.1f s" % (name, time.time() - t0), flush=True)
         dev = _dev()
         ob = torch.int32 if g.indices.shape[0] < 2**31 else torch.int64
         o = torch.from_numpy(g.offsets).to(dev).to(ob)
@@ -42,6 +70,10 @@ def _workload(name):
         m = torch.from_numpy(g.membership).to(dev)
         _CACHE[name] = (g, o, a, m)
     return _CACHE[name]
+
+
+def _rec_key(r):
+    return sorted(tuple(int(x) for x in (q["minv"], q["n"], q["k"], q["lam"], q["ssize"], q["shash"])) for q in r)
 
 
 def _canon(labels, mask=None):
@@ -63,83 +95,96 @@ def _k_log10(n):
     return np.floor(np.log10(np.maximum(n, 1))).astype(np.int64) + 1  # exact for n < 1e15
 
 
-def _sample_clusters(memb, seed, n_small=400, n_mid=4):
+def test_c2_whole_workload_parity():
+    import paper_2509_02590_amd as w
+    g, o, a, m = _workload("c2")
+    got, st, rec = w.wcc_run(o, a, m, records_cap=4_000_000)
+    got = got.cpu().numpy()
+    print("c2 plain: %.0f ms, %d sets, %d records" % (st.ms_total, st.accepted, len(rec)), flush=True)
+    bat, stb, recb = w.wcc_run(o, a, m, exec_mode="batched", graph=False, records_cap=4_000_000)
+    print("c2 batched: %.0f ms" % stb.ms_total, flush=True)
+    assert np.array_equal(bat.cpu().numpy(), got), "batched differs from plain"
+    assert _rec_key(recb) == _rec_key(rec), "batched records differ from plain"
+    sizes = np.bincount(g.membership[g.membership >= 0])
+    assert sizes.max() > 50_000                       # the global-state path is exercised
+    t0 = time.time()
+    want, wrec = oracle.wcc(g, nthreads=_threads())
+    print("oracle on the whole workload: %.1f s on %d threads" % (time.time() - t0, _threads()), flush=True)
+    assert np.array_equal(got, want), "membership differs in %d vertices" % int((got != want).sum())
+    assert len(rec) == len(wrec)
+    assert _rec_key(rec) == _rec_key(wrec), "split records differ"
+    assert int(rec["n"].max()) > 16384                 # the summary-level scan was compared
+    assert np.all(rec["k"] == _k_log10(rec["n"]))
+
+
+def _mid_graph():
+    """Four clusters of 23k-59k vertices, most with planted bridges nested up to three
+    levels deep (the 1M-vertex workload's recipe at larger cluster sizes)."""
+    return gen.chung_lu(160000, 30.0, 2.5, 20000, 60000, 1.5, 0.2, 0.6, 0.0, 3, seed=4242, intra_mult=1.2)
+
+
+@pytest.mark.parametrize("mode,crit", [("kcore", "log10"), ("kcore", "log2"), ("paper", "log10")])
+def test_mid_size_clusters(mode, crit):
+    import paper_2509_02590_amd as w
+    g = _mid_graph()
+    dev = _dev()
+    o = torch.from_numpy(g.offsets.astype(np.int32)).to(dev)
+    a = torch.from_numpy(g.indices).to(dev)
+    m = torch.from_numpy(g.membership).to(dev)
+    t0 = time.time()
+    want, wrec = oracle.wcc(g, mode=mode, criterion=crit, nthreads=_threads())
+    print("oracle %s %s: %.1f s, %d records" % (mode, crit, time.time() - t0, len(wrec)), flush=True)
+    for exec_mode in ("plain", "batched"):
+        got, st, rec = w.wcc_run(o, a, m, mode=mode, criterion=crit, exec_mode=exec_mode, graph=False,
+                                 records_cap=200_000)
+        got = got.cpu().numpy()
+        assert np.array_equal(got, want), (exec_mode, int((got != want).sum()))
+        assert _rec_key(rec) == _rec_key(wrec), exec_mode
+    if mode == "kcore" and crit == "log10":
+        assert int(wrec["n"].max()) > 16384
+
+
+def _sample_clusters(memb, seed, n_small=400, n_mid=6, n_top=3):
+    """Random small and mid-size clusters plus the n_top largest ones."""
     sizes = np.bincount(memb[memb >= 0])
     rng = np.random.default_rng(seed)
     ids = np.nonzero(sizes > 0)[0]
     small = ids[sizes[ids] <= 3000]
-    mid = ids[(sizes[ids] > 3000) & (sizes[ids] <= 8000)]
-    return np.concatenate([rng.choice(small, min(n_small, len(small)), replace=False),
-                           rng.choice(mid, min(n_mid, len(mid)), replace=False)])
+    mid = ids[(sizes[ids] > 3000) & (sizes[ids] <= 50000)]
+    top = ids[np.argsort(-sizes[ids], kind="stable")[:n_top]]
+    return np.unique(np.concatenate([rng.choice(small, min(n_small, len(small)), replace=False),
+                                     rng.choice(mid, min(n_mid, len(mid)), replace=False), top]))
 
 
-def _label_graph(g, lab, chunk=200_000_000):
-    """CSR of the entries whose two ends carry the same label (>= 0), built row-chunk by
-    row-chunk so that 4e9-entry inputs stay within host memory."""
-    n = g.n
-    off = g.offsets
-    cnt = np.zeros(n, np.int64)
-    parts = []
-    r0 = 0
-    while r0 < n:
-        r1 = int(np.searchsorted(off, off[r0] + chunk, side="right")) - 1
-        r1 = max(r1, r0 + 1)
-        r1 = min(r1, n)
-        e0, e1 = off[r0], off[r1]
-        src = np.repeat(np.arange(r0, r1, dtype=np.int32), np.diff(off[r0:r1 + 1]))
-        dst = g.indices[e0:e1]
-        ls = lab[src]
-        keep = (ls >= 0) & (ls == lab[dst])
-        cnt[r0:r1] = np.bincount(src[keep] - r0, minlength=r1 - r0)
-        parts.append(dst[keep])
-        r0 = r1
-        if len(off) > 50_000_000:
-            print("label graph: rows up to %d of %d" % (r0, n), flush=True)
-    off2 = np.zeros(n + 1, np.int64)
-    np.cumsum(cnt, out=off2[1:])
-    return off2, np.concatenate(parts) if parts else np.zeros(0, np.int32)
-
-
-@pytest.mark.parametrize("name", WORKLOADS)
-def test_full_size_sampled_parity(name):
+def test_c4_sampled_parity():
+    avail = _mem_available()
+    if avail < C4_HOST_BYTES:
+        pytest.skip("2B-edge workload needs %.0f GiB of host memory, %.0f GiB available"
+                    % (C4_HOST_BYTES / 2**30, avail / 2**30))
     import paper_2509_02590_amd as w
-    g, o, a, m = _workload(name)
-    got, st, rec = w.wcc_run(o, a, m, records_cap=4_000_000)
+    g, o, a, m = _workload("c4")
+    got, st, rec = w.wcc_run(o, a, m, records_cap=8_000_000)
     got = got.cpu().numpy()
-    print("%s plain: %.0f ms, %d sets" % (name, st.ms_total, st.accepted), flush=True)
+    print("c4 plain: %.0f ms, %d sets, %d records" % (st.ms_total, st.accepted, len(rec)), flush=True)
     bat, stb, _ = w.wcc_run(o, a, m, exec_mode="batched", graph=False)
-    print("%s batched: %.0f ms" % (name, stb.ms_total), flush=True)
+    print("c4 batched: %.0f ms" % stb.ms_total, flush=True)
     assert np.array_equal(bat.cpu().numpy(), got), "batched differs from plain"
     memb = g.membership
-    sizes = np.bincount(memb[memb >= 0])
-    assert sizes.max() > 50_000  # the global-state path is exercised
-
-    # 1) oracle on sampled whole clusters
     pick = _sample_clusters(memb, 20)
+    sizes = np.bincount(memb[memb >= 0])
+    assert sizes[pick].max() == sizes.max() > 900_000     # the largest cluster is in the sample
     memb_s = np.where(np.isin(memb, pick), memb, -1).astype(np.int32)
-    want, _ = oracle.wcc(g.offsets, g.indices, memb_s)
-    print("oracle on %d sampled clusters done" % len(pick), flush=True)
+    t0 = time.time()
+    want, wrec = oracle.wcc(g.offsets, g.indices, memb_s, nthreads=_threads())
+    print("oracle on %d sampled clusters (%d vertices, largest %d): %.1f s on %d threads"
+          % (len(pick), int((memb_s >= 0).sum()), int(sizes[pick].max()), time.time() - t0, _threads()),
+          flush=True)
     mask = memb_s >= 0
     assert np.array_equal(_canon(got, mask), _canon(want)), "sampled clusters differ from the oracle"
-
-    # 2) properties of every output set
-    lab = got.astype(np.int32)
-    on = lab >= 0
-    nsets = int(lab.max()) + 1
-    assert nsets == st.accepted
-    size = np.bincount(lab[on], minlength=nsets)
-    assert size.min() > 10                                   # larger than s_post
-    rep = np.full(nsets, np.iinfo(np.int64).max, np.int64)
-    np.minimum.at(rep, lab[on], np.nonzero(on)[0])         # smallest vertex of each set
-    assert np.all(memb[on] == memb[rep[lab[on]]])            # inside one input cluster
-    off2, adj2 = _label_graph(g, lab)
-    din = np.diff(off2)
-    assert np.all(din[on] >= _k_log10(size[lab[on]]))        # KCORE: each set is a k(n)-core
-    comp = oracle.components(off2, adj2, alive=on.astype(np.uint8))
-    print("components of the output sets done", flush=True)
-    assert np.array_equal(np.unique(comp[on]).size, nsets)   # each set connected, sets disjoint
-    assert np.all(comp[on] == rep[lab[on]])                  # (component = labelled set)
-    # the cut records: accepted sets have lambda >= k(n); k(n) is the log10 rule
+    # records of the sampled clusters (a record's smallest vertex names its input cluster)
+    sel = np.isin(memb[rec["minv"]], pick)
+    assert _rec_key(rec[sel]) == _rec_key(wrec), "split records of the sampled clusters differ"
+    assert int(wrec["n"].max()) > 100_000
     acc = rec["lam"] >= rec["k"]
     assert acc.sum() == st.accepted
     assert np.all(rec["k"] == _k_log10(rec["n"]))
@@ -160,35 +205,32 @@ def _cm_sets(comp):
     return verts, set_off, caps
 
 
-@pytest.mark.parametrize("name", WORKLOADS)
-def test_cm_split_batch_full_size(name):
-    """CCR labels of sampled clusters and cuts of sampled CCR components, against the oracle."""
+def test_cm_split_batch_full_size():
+    """CCR labels of every cluster and cuts of sampled CCR components (the largest
+    included), against the oracle."""
     import paper_2509_02590_amd as w
-    g, o, a, m = _workload(name)
+    g, o, a, m = _workload("c2")
     comp = w.ccr_components(o, a, m)
     comp_h = comp.cpu().numpy()
     memb = g.membership
-    pick = _sample_clusters(memb, 21, n_small=300, n_mid=2)
-    sel = np.isin(memb, pick)
-    deg = np.diff(g.offsets)
-    rows = np.nonzero(sel)[0]
-    # oracle components of the sampled clusters' intra-cluster graph
-    src = np.repeat(rows.astype(np.int64), deg[rows])
-    dst = np.concatenate([g.indices[g.offsets[v]:g.offsets[v + 1]] for v in rows]) if len(rows) else \
-        np.zeros(0, np.int32)
-    keep = memb[dst] == memb[src]
+    # oracle components of the whole intra-cluster graph
+    src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.offsets))
+    keep = (memb[src] >= 0) & (memb[g.indices] == memb[src])
     cnt = np.bincount(src[keep], minlength=g.n)
     off2 = np.zeros(g.n + 1, np.int64)
     np.cumsum(cnt, out=off2[1:])
-    want = oracle.components(off2, dst[keep].astype(np.int32), alive=sel.astype(np.uint8))
-    assert np.array_equal(np.where(sel, comp_h, -1), want)
+    want = oracle.components(off2, g.indices[keep], alive=(memb >= 0).astype(np.uint8))
+    del src, keep
+    assert np.array_equal(comp_h, want)
     verts, set_off, caps = _cm_sets(comp)
     lam, side = w.mincut_split_batch(o, a, verts, set_off, caps)
     lam, side = lam.cpu().numpy(), side.cpu().numpy().astype(bool)
     so, vh, ch = set_off.cpu().numpy(), verts.cpu().numpy(), caps.cpu().numpy()
     rng = np.random.default_rng(5)
-    small = np.nonzero(np.diff(so) <= 2000)[0]
-    for i in rng.choice(small, min(40, len(small)), replace=False):
+    sz = np.diff(so)
+    small = np.nonzero(sz <= 2000)[0]
+    pick = np.concatenate([rng.choice(small, min(40, len(small)), replace=False), np.argsort(-sz)[:2]])
+    for i in pick:
         vs = vh[so[i]:so[i + 1]]
         wl, ws = oracle.mincut_split(g.offsets, g.indices, vs, int(ch[i]))
         assert lam[i] == wl, i
