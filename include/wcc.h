@@ -290,6 +290,23 @@ int wcc_cm_run(const wcc_csr *g, const int32_t *membership_in, const wcc_params 
  */
 int wcc_cda(const wcc_csr *g, const int32_t *part_of, const wcc_cm_params *cm, int32_t *comm_out, void *stream);
 
+/*
+ * wcc_run_noalloc -- wcc_run for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, outputs and results as wcc_run in the plain execution form (p->exec_mode is
+ * ignored).  The caller still passes every input and output; the library's workspace
+ * is a fixed 64 MiB device array per GPU (allocated when the library is loaded and held
+ * until the process ends), so the input is limited to 65,536 vertices and 1,048,576 CSR
+ * entries.  The first call on a device sets up its streams and events; no call allocates
+ * or frees device memory.  Every call on a GPU shares that GPU's array, so calls that
+ * overlap on one GPU race; calls are serialised by the library's lock, and the array's
+ * contents after a call are unspecified (each call starts from its own inputs).
+ * Errors: as wcc_run; WCC_EUNSUPPORTED for inputs beyond the limits (nothing is launched).
+ */
+int wcc_run_noalloc(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, int32_t *membership_out,
+                    wcc_stats *stats, wcc_record *records, int64_t records_cap, int64_t *num_records,
+                    void *stream);
+
 /* Threshold k(n) used by the library for the given criterion (host function). */
 int64_t wcc_threshold(int32_t criterion, int64_t n, int32_t lin_num, int32_t lin_den);
 

@@ -140,6 +140,8 @@ class CmParams(ctypes.Structure):
     _fields_ = [("cda", ctypes.c_int32), ("cda_iters", ctypes.c_int32), ("fn", CDA_FN), ("user", _vp)]
 
 
+lib.wcc_run_noalloc.restype = ctypes.c_int
+lib.wcc_run_noalloc.argtypes = lib.wcc_run.argtypes
 lib.wcc_cm_run.restype = ctypes.c_int
 lib.wcc_cm_run.argtypes = [ctypes.POINTER(Csr), _vp, ctypes.POINTER(Params), ctypes.POINTER(CmParams), _vp,
                            ctypes.POINTER(Stats), _vp, _i64, ctypes.POINTER(ctypes.c_int64), _vp]
@@ -181,8 +183,10 @@ def params(criterion="log10", s_pre=10, s_post=10, mode="kcore", exec_mode="plai
     return p
 
 
-def wcc_run(offsets, indices, membership, *, out=None, records_cap=0, **kw):
-    """WCC over a device CSR and membership -> (membership_out, Stats, records or None)."""
+def wcc_run(offsets, indices, membership, *, out=None, records_cap=0, noalloc=False, **kw):
+    """WCC over a device CSR and membership -> (membership_out, Stats, records or None).
+    noalloc=True calls wcc_run_noalloc (fixed workspace; small inputs only; pass `out`
+    and a records buffer size of 0 to make the call itself allocate nothing)."""
     import torch
     g = make_csr(offsets, indices)
     assert membership.is_cuda and membership.dtype == torch.int32 and membership.numel() == g.num_vertices
@@ -194,7 +198,8 @@ def wcc_run(offsets, indices, membership, *, out=None, records_cap=0, **kw):
     nrec = ctypes.c_int64(0)
     if records_cap:
         rec = torch.empty(records_cap * RECORD_DTYPE.itemsize, dtype=torch.uint8, device=membership.device)
-    rc = lib.wcc_run(ctypes.byref(g), membership.data_ptr() if membership.numel() else None,
+    fn = lib.wcc_run_noalloc if noalloc else lib.wcc_run
+    rc = fn(ctypes.byref(g), membership.data_ptr() if membership.numel() else None,
                      ctypes.byref(p), out.data_ptr() if out.numel() else None, ctypes.byref(st),
                      rec.data_ptr() if rec is not None else None, records_cap, ctypes.byref(nrec),
                      _stream(torch, membership.device))

@@ -27,11 +27,28 @@ namespace {
 // holds raw buffer addresses and is only replayed while this value is unchanged.
 std::atomic<unsigned long long> g_alloc_gen{1};
 
+// A fixed device region that buffers are carved from in call order (the allocation-free
+// entry point): a buffer that must grow takes a new slice, nothing is ever freed, and the
+// carve restarts at the next call.
+struct Carver {
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+};
+
 struct Buf {
   void *p = nullptr;
   size_t bytes = 0;
+  Carver *carve = nullptr;
   int ensure(size_t b) {
     if (b <= bytes) return WCC_OK;
+    if (carve) {
+      size_t off = (carve->used + 255) & ~(size_t)255;
+      if (off > carve->size || b > carve->size - off) return WCC_ENOMEM;
+      p = carve->base + off;
+      bytes = b;
+      carve->used = off + b;
+      return WCC_OK;
+    }
     g_alloc_gen++;
     if (p) (void)hipFree(p);
     p = nullptr;
@@ -45,7 +62,7 @@ struct Buf {
     return WCC_OK;
   }
   void release() {
-    if (p) {
+    if (p && !carve) {
       g_alloc_gen++;
       (void)hipFree(p);
     }
@@ -423,6 +440,13 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
     int grid_big = nbig < w.cus ? nbig : w.cus;
     // bitmap regions of the large-bin workgroups (small-bin items keep their state in LDS)
     int64_t words = hs.maxbits > 0 ? hs.maxbits : 1;
+    Carver *cv = w.b[B_GBITS].carve;
+    if (cv && grid_big > 1) {
+      // a fixed region: fewer large-bin workgroups (each loops over the large items)
+      size_t left = cv->size > cv->used + 512 ? cv->size - cv->used - 512 : 0;
+      int64_t fit = (int64_t)(left / ((size_t)words * 8 + 64));
+      if (fit < grid_big) grid_big = fit > 1 ? (int)fit : 1;
+    }
     TRY(w.b[B_GBITS].ensure((size_t)(grid_big > 0 ? grid_big : 1) * words * 8 + 64));
     ItemArgs A = base;
     A.gbits = w.b[B_GBITS].as<uint64_t>();
@@ -1349,6 +1373,55 @@ int cm_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params &p, const 
 
 }  // namespace
 
+static thread_local char g_detail[512] = "";
+
+// ---------------------------------------------------------------- allocation-free entry
+// The workspace of wcc_run_noalloc lives in this array: one copy per GPU, held until the
+// process ends.  Host code never uses the name as an address (on the host it is only a
+// stand-in for the symbol): the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+constexpr int64_t NOALLOC_MAX_VERTICES = 1 << 16;
+constexpr int64_t NOALLOC_MAX_ENTRIES = 1 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+struct NoallocDev {
+  Workspace *w = nullptr;
+  Carver carve;
+};
+std::vector<NoallocDev> g_noalloc;
+
+// Set-up on the first call on a device: the scratch array's device address, and a
+// workspace (streams, events) whose buffers are carved from it.
+int noalloc_setup(NoallocDev **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if ((int)g_noalloc.size() <= dev) g_noalloc.resize(dev + 1);
+  NoallocDev &nd = g_noalloc[dev];
+  if (!nd.w) {
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return WCC_EHIP;
+    Workspace *w = new Workspace();
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    int rc = ws_init(*w, dev, prop);
+    if (rc) {
+      w->destroy();
+      delete w;
+      return rc;
+    }
+    nd.carve.base = (char *)ptr;
+    nd.carve.size = NOALLOC_SCRATCH_BYTES;
+    for (auto &b : w->b) b.carve = &nd.carve;
+    nd.w = w;
+  }
+  *out = &nd;
+  return WCC_OK;
+}
+}  // namespace
+
 // ---------------------------------------------------------------- served form
 struct wcc_server {
   struct Job {
@@ -1465,7 +1538,6 @@ struct wcc_server {
   }
 };
 
-static thread_local char g_detail[512] = "";
 
 void wcc_note_hip_error(hipError_t e, const char *expr, const char *file, int line) {
   const char *base = strrchr(file, '/');
@@ -1527,6 +1599,39 @@ int wcc_ccr_components(const wcc_csr *g, const int32_t *membership_in, int32_t *
   std::lock_guard<std::mutex> lk(g_lock);
   try {
     return ccr_impl(g, membership_in, comp_out, (hipStream_t)stream);
+  } catch (...) {
+    return WCC_ENOMEM;
+  }
+}
+
+int wcc_run_noalloc(const wcc_csr *g, const int32_t *membership_in, const wcc_params *p, int32_t *membership_out,
+                    wcc_stats *stats, wcc_record *records, int64_t records_cap, int64_t *num_records,
+                    void *stream) {
+  std::lock_guard<std::mutex> lk(g_lock);
+  try {
+    int rc = check_csr(g);
+    if (rc) return rc;
+    if (g->num_vertices > NOALLOC_MAX_VERTICES || g->num_entries > NOALLOC_MAX_ENTRIES) {
+      snprintf(g_detail, sizeof(g_detail),
+               "wcc_run_noalloc: %lld vertices / %lld entries exceed its limits (%lld / %lld)",
+               (long long)g->num_vertices, (long long)g->num_entries, (long long)NOALLOC_MAX_VERTICES,
+               (long long)NOALLOC_MAX_ENTRIES);
+      return WCC_EUNSUPPORTED;
+    }
+    NoallocDev *nd;
+    TRY(noalloc_setup(&nd));
+    // every call carves the workspace afresh from the start of the array
+    nd->carve.used = 0;
+    for (auto &b : nd->w->b) {
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    wcc_params pp;
+    if (p) pp = *p;
+    else wcc_default_params(&pp);
+    pp.exec_mode = WCC_EXEC_PLAIN;  // (a recorded graph would be an allocation)
+    return wcc_run_impl(*nd->w, g, membership_in, &pp, membership_out, stats, records, records_cap, num_records,
+                        (hipStream_t)stream);
   } catch (...) {
     return WCC_ENOMEM;
   }
