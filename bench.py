@@ -1,15 +1,19 @@
 """Benchmark of the WCC hot path on one MI355X.
 
 A step is one whole wcc_run (front end, CCR, pruning, every minimum cut and split, and the
-final relabel) over the 1M-vertex / 20M-edge Chung-Lu workload with a planted power-law
-clustering (input already resident in HBM).  Prints ONE JSON line.
+final relabel) over the 250M-vertex / 2B-edge Chung-Lu workload with a planted power-law
+clustering (the largest single-GPU configuration, on which batched and plain execution
+are compared), input already resident in HBM.  Prints ONE JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c0|c2|served]
-                  [--exec batched|plain] [--no-compare] [--mode kcore|paper] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c1|c0|served]
+                  [--exec batched|plain] [--no-compare] [--compare-steps C] [--mode kcore|paper]
+                  [--no-cpu-baseline] [--autotune]
 
 The timed form (default batched: device-driven level launches replayed from a HIP
-graph) gives `value`; the other form is timed after it on the same input and reported in
-`other_exec` together with whether both produced the same membership.
+graph) gives `value`; the other form is timed after it on the same input (C steps after
+one warmup run) and reported in `other_exec` together with whether both produced the
+same membership.  The launch shape is the library's default; --autotune times every
+candidate shape on the input first (minutes on the 2B-edge workload).
 """
 import argparse
 import json
@@ -180,22 +184,66 @@ def cm_split(g, off, idx, mem, wcc, torch, reps):
             "ms_split_batch": 1000.0 * best, "edges_per_s": g.m / best, "below_cap": below}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def sample_clusters(memb, seed=20, n_small=400, n_mid=6, n_top=3):
+    """Whole input clusters: random small and mid-size ones plus the n_top largest."""
+    import numpy as np
+    sizes = np.bincount(memb[memb >= 0])
+    rng = np.random.default_rng(seed)
+    ids = np.nonzero(sizes > 0)[0]
+    small = ids[sizes[ids] <= 3000]
+    mid = ids[(sizes[ids] > 3000) & (sizes[ids] <= 50000)]
+    top = ids[np.argsort(-sizes[ids], kind="stable")[:n_top]]
+    return np.unique(np.concatenate([rng.choice(small, min(n_small, len(small)), replace=False),
+                                     rng.choice(mid, min(n_mid, len(mid)), replace=False), top]))
+
+
 def cpu_baseline(g, mode, threads):
-    """The oracle, as it stands, on the same workload (one full run)."""
+    """The oracle, as it stands, on the same workload: one full run when the workload has
+    at most 2.5e8 edges, else on a sample of whole input clusters that includes the
+    largest ones (WCC treats clusters independently).  Edges counted: the input edges
+    whose rows the oracle scans (entries of the sampled vertices' rows, halved)."""
+    import numpy as np
     import oracle
+    if g.m <= 250_000_000:
+        t0 = time.perf_counter()
+        oracle.wcc(g, s_pre=10, s_post=10, mode=mode, nthreads=threads, log=False)
+        dt = time.perf_counter() - t0
+        return {"value": g.m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+                "sample": "one full run of the same %s workload (%d edges), %.2f s" % (g.meta["workload"], g.m, dt)}
+    memb = g.membership
+    pick = sample_clusters(memb)
+    sel = np.isin(memb, pick)
+    memb_s = np.where(sel, memb, -1).astype(np.int32)
+    m_s = int(np.diff(g.offsets)[sel].sum()) // 2
+    sizes = np.bincount(memb[memb >= 0])
     t0 = time.perf_counter()
-    oracle.wcc(g, s_pre=10, s_post=10, mode=mode, nthreads=threads, log=False)
+    oracle.wcc(g.offsets, g.indices, memb_s, s_pre=10, s_post=10, mode=mode, nthreads=threads, log=False)
     dt = time.perf_counter() - t0
-    return {"value": g.m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": "one full run of the same %s workload (%d edges), %.2f s" % (g.meta["workload"], g.m, dt)}
+    return {"value": m_s / dt, "unit": "edges/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": "%d whole input clusters of the %s workload (%d vertices, %d edges in their rows, "
+                      "largest cluster %d vertices), %.2f s" % (len(pick), g.meta["workload"], int(sel.sum()), m_s,
+                                                                 int(sizes[pick].max()), dt)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--workload", default="c4")
+    ap.add_argument("--compare-steps", type=int, default=5,
+                    help="timed steps of the other execution form (after one warmup run)")
     ap.add_argument("--exec", dest="exec_mode", default="batched")
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip timing the other execution form")
@@ -205,8 +253,10 @@ def main():
     ap.add_argument("--served-exec", default="plain", help="served: execution form of each job")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="served: arrivals per second (default: twice the plain path's capacity)")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="keep the default launch shape instead of tuning it on this input first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every candidate launch shape on this input first (else: the tune file's shape "
+                         "for this device and input, or the default shape)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cm", action="store_true",
                     help="also time the CM-style mincut_split_batch over every CCR component")
@@ -261,33 +311,35 @@ def main():
         tuned = {"shape": shape, "best_ms": tms, "shapes_timed": ntried, "seconds": time.perf_counter() - t0}
         log("autotune: %s (%.2f ms, %d shapes, %.1f s)" % (shape, tms, ntried, tuned["seconds"]))
 
-    def timed(exec_mode):
+    def timed(exec_mode, steps, warmup):
         kw = dict(s_pre=10, s_post=10, mode=args.mode, exec_mode=exec_mode)
-        for i in range(args.warmup):
+        for i in range(warmup):
             wcc.wcc_run(off, idx, mem, out=out, **kw)
             log("%s warmup %d done" % (exec_mode, i))
         torch.cuda.synchronize()
         stats = []
         t_start = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             _, st, _ = wcc.wcc_run(off, idx, mem, out=out, **kw)
             stats.append(st.as_dict())
+            if g.m > 250_000_000:
+                log("%s step %d: %.1f ms" % (exec_mode, i, st.ms_total))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         log("%s: timed %d steps: %.2f ms/step, %.3e edges/s"
-            % (exec_mode, args.steps, 1000.0 * elapsed / args.steps, g.m * args.steps / elapsed))
+            % (exec_mode, steps, 1000.0 * elapsed / steps, g.m * steps / elapsed))
         return elapsed, stats, out.clone()
 
-    elapsed, stats, res = timed(args.exec_mode)
+    elapsed, stats, res = timed(args.exec_mode, args.steps, args.warmup)
     ms_step = 1000.0 * elapsed / args.steps
     value = g.m / (elapsed / args.steps)
     other = None
     if args.compare:
         other_mode = "plain" if args.exec_mode == "batched" else "batched"
-        o_elapsed, o_stats, o_res = timed(other_mode)
-        other = {"exec": other_mode, "value": g.m / (o_elapsed / args.steps),
-                 "ms_per_step": 1000.0 * o_elapsed / args.steps,
-                 "equal_output": bool(torch.equal(res, o_res))}
+        cs = max(1, args.compare_steps)
+        o_elapsed, o_stats, o_res = timed(other_mode, cs, 1)
+        other = {"exec": other_mode, "value": g.m / (o_elapsed / cs), "steps": cs, "warmup": 1,
+                 "ms_per_step": 1000.0 * o_elapsed / cs, "equal_output": bool(torch.equal(res, o_res))}
 
     # roofline of the dominant kernel (the per-item kernel), timed with HIP events that
     # the library records around every item launch on the stream it is launched on
@@ -301,15 +353,29 @@ def main():
                             TRAFFIC["workload"] == g.meta["workload"] and TRAFFIC["exec"] == args.exec_mode
                             and TRAFFIC["mode"] == args.mode):
         traffic = TRAFFIC["bytes_per_launch"]
+    # whole-job floor: one pass over the input (index + neighbour-cluster gather per entry,
+    # offsets + membership + output per vertex)
+    obytes = 4 if obits == np.int32 else 8
+    b_floor = g.indices.shape[0] * 8 + g.n * (obytes + 4 + 4)
+    t_step = elapsed / args.steps
+    b_alg_step = b_floor + s0["item_alg_bytes"]
+    # "bound" names the roofline the fraction is taken against: the item kernel moves
+    # integers only (no MFMA work, little ALU work), so HBM bandwidth is its only
+    # roofline; what limits it is latency (one dependent chain of scan steps per item),
+    # which is why the fraction is small ("limiter")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_items",
+                "kernel": "k_items", "limiter": "latency (dependent maximum-adjacency scan steps)",
                 "avg_launch_ms": avg_launch_s * 1e3,
-                "alg_bytes_per_launch": alg_bytes_per_launch, "launches_per_step": s0["item_launches"]}
-
-    # whole-job floor: one pass over the input (index + neighbour-cluster gather per entry,
-    # offsets + membership + output per vertex), for context
-    b_floor = g.indices.shape[0] * 8 + g.n * (4 + 4 + 4)
+                "alg_bytes_per_launch": alg_bytes_per_launch, "launches_per_step": s0["item_launches"],
+                "step_fractions": {
+                    "floor": b_floor / t_step / 1e9 / HBM_PEAK_GBS,
+                    "alg": b_alg_step / t_step / 1e9 / HBM_PEAK_GBS,
+                    "counters": (traffic * s0["item_launches"] / t_step / 1e9 / HBM_PEAK_GBS
+                                 if traffic is not None else None),
+                    "note": "whole step: one input pass (floor), that plus the item launches' "
+                            "algorithmic bytes (alg), the item launches' counter-measured bytes "
+                            "(counters), each over the step time and 8 TB/s"}}
     line = {
         "metric": METRIC,
         "value": value,

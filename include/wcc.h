@@ -323,6 +323,13 @@ typedef struct {
   int32_t big_lds_kb;   /* dynamic LDS of a large-bin workgroup (one per CU), <= 159 KB */
   int32_t big_max_pct;  /* BATCHED: at most this share of the CUs (percent) runs
                            large-bin workgroups; 0 = no large-bin launch (default 100) */
+  int32_t chain_min_n;  /* BATCHED: a workgroup that splits an item goes on with its largest
+                           child itself (without waiting for the level to end) when that child
+                           has at least this many vertices and belongs to the workgroup's size
+                           bin; INT32_MAX = never; -1 (default) = automatic: every child when
+                           the large items are at most four times the large-bin workgroups
+                           (few long chains), never otherwise (the children of many large
+                           items are better spread over the next level) */
 } wcc_exec_config;
 
 /* Current shape (host out).  Environment variables WCC_LDS_KB, WCC_WG_PER_CU,

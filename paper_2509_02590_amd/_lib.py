@@ -68,7 +68,8 @@ class Stats(ctypes.Structure):
 
 class ExecConfig(ctypes.Structure):
     _fields_ = [("small_lds_kb", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("big_lds_kb", ctypes.c_int32), ("big_max_pct", ctypes.c_int32)]
+                ("big_lds_kb", ctypes.c_int32), ("big_max_pct", ctypes.c_int32),
+                ("chain_min_n", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -98,11 +98,13 @@ struct ExecCfg : wcc_exec_config {
     wg_per_cu = 0;
     big_lds_kb = 159;
     big_max_pct = 100;
+    chain_min_n = -1;
   }
 };
 bool cfg_valid(const wcc_exec_config &c) {
   return c.small_lds_kb >= 4 && c.small_lds_kb <= 64 && c.wg_per_cu >= 0 && c.wg_per_cu <= 8 &&
-         c.big_lds_kb >= c.small_lds_kb && c.big_lds_kb <= 159 && c.big_max_pct >= 0 && c.big_max_pct <= 100;
+         c.big_lds_kb >= c.small_lds_kb && c.big_lds_kb <= 159 && c.big_max_pct >= 0 && c.big_max_pct <= 100 &&
+         c.chain_min_n >= -1;
 }
 
 // Identity of a recorded batched run: replayed only for the same buffers and parameters.
@@ -122,6 +124,7 @@ struct BatchPlan {
   int g_big = 0, g_small = 0;
   int64_t gbits_words = 0;
   int64_t capS = 0, capB = 0;  // list capacities (items)
+  int32_t chain_min_n = 0x7fffffff;  // chained form: least child size kept by its workgroup
   int levels = 0;              // levels launched (a multiple of the chunk size)
 };
 
@@ -199,6 +202,7 @@ int ws_init(Workspace &w, int dev, const hipDeviceProp_t &prop) {
   w.cfg.big_lds_kb = env_int("WCC_BIG_LDS_KB", w.cfg.big_lds_kb);
   w.cfg.wg_per_cu = env_int("WCC_WG_PER_CU", w.cfg.wg_per_cu);
   w.cfg.big_max_pct = env_int("WCC_BIG_PCT", w.cfg.big_max_pct);
+  w.cfg.chain_min_n = env_int("WCC_CHAIN_MIN", w.cfg.chain_min_n);
   return WCC_OK;
 }
 
@@ -562,6 +566,11 @@ int plan_batched(Workspace &w, const wcc_params &p, int64_t N, int32_t nitems, B
   pl->g_big = pl->nbig < cap_big ? pl->nbig : cap_big;
   if (pl->g_big == 0) pl->nbig = 0;
   pl->g_small = w.cus * shp.per_cu;
+  // chained form: with few large items per large-bin workgroup the level time is one long
+  // chain of splits, which chaining shortens; with many, chaining only holds back the
+  // children left for the next level
+  pl->chain_min_n = w.cfg.chain_min_n >= 0 ? w.cfg.chain_min_n
+                    : (pl->nbig <= 4 * (int64_t)(pl->g_big > 0 ? pl->g_big : 1) ? 0 : 0x7fffffff);
   // (the bitmap bound of the initial items covers their descendants: smaller sets with
   // caps no larger)
   pl->gbits_words = maxbits;
@@ -616,6 +625,8 @@ int launch_levels(Workspace &w, const ItemArgs &base, const BatchPlan &pl, int L
     A.out_big_count = ctl + 2 * nx + 1;
     A.out_big_cap = (int32_t)pl.capB;
     A.small_words = pl.small_words;
+    A.chain = 1;
+    A.chain_min_n = pl.chain_min_n;
     A.gbits_words = pl.gbits_words;
     if (pl.g_big > 0) {
       // largest first (level 0 is sorted already) so that the longest items start at once;
@@ -693,16 +704,18 @@ int finish_levels(Workspace &w, const ItemArgs &base, BatchPlan &pl, int *L, boo
 int levels_kernel_ms(Workspace &w, const BatchPlan &pl, int L, double *ms, int64_t *launches) {
   double tot = 0;
   int64_t n = 0;
+  bool verbose = env_int("WCC_VERBOSE", 0) != 0;
   for (int l = 0; l < L && l < MAX_TIMED_LEVELS; l++) {
-    float a = 0;
+    float a = 0, b = 0;
     if (pl.g_big > 0) {
       if (hipEventElapsedTime(&a, w.lev[l][0], w.lev[l][1]) != hipSuccess) goto fail;
       tot += a;
       n++;
     }
-    if (hipEventElapsedTime(&a, w.lev[l][2], w.lev[l][3]) != hipSuccess) goto fail;
-    tot += a;
+    if (hipEventElapsedTime(&b, w.lev[l][2], w.lev[l][3]) != hipSuccess) goto fail;
+    tot += b;
     n++;
+    if (verbose) fprintf(stderr, "[wcc] batched level %d: large bin %.2f ms, small bin %.2f ms\n", l + 1, a, b);
   }
   *ms = tot;
   *launches = n;
@@ -1071,12 +1084,14 @@ bool tune_cache_lookup(const char *path, const std::string &key, ExecCfg *c) {
   bool found = false;
   while (fgets(line, sizeof(line), f)) {
     char k[600];
-    int a, b, d, e;
-    if (sscanf(line, "%599s %d %d %d %d", k, &a, &b, &d, &e) == 5 && key == k) {
+    int a, b, d, e, cm = c->chain_min_n;
+    int got = sscanf(line, "%599s %d %d %d %d %d", k, &a, &b, &d, &e, &cm);
+    if (got >= 5 && key == k) {
       c->small_lds_kb = a;
       c->wg_per_cu = b;
       c->big_lds_kb = d;
       c->big_max_pct = e;
+      c->chain_min_n = cm;
       found = cfg_valid(*c);  // the last valid entry for the key wins
     }
   }
@@ -1143,7 +1158,8 @@ int autotune_impl(const wcc_csr *g, const int32_t *mem_in, const wcc_params *pp,
   if (cache && *cache) {
     FILE *f = fopen(cache, "a");
     if (f) {
-      fprintf(f, "%s %d %d %d %d\n", key.c_str(), win.small_lds_kb, win.wg_per_cu, win.big_lds_kb, win.big_max_pct);
+      fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), win.small_lds_kb, win.wg_per_cu, win.big_lds_kb, win.big_max_pct,
+              win.chain_min_n);
       fclose(f);
     }
   }

@@ -157,6 +157,10 @@ struct ItemArgs {
   // PAPER mode: items with a vertex of degree 1 are peeled to their 2-core in one batch
   // (every step of the one-at-a-time peel fails its cut: k(s_post + 1) >= 2)
   int32_t leaf_batch;
+  // chained form (batched execution): a workgroup that splits an item processes one of the
+  // children itself, next, instead of leaving every child to the next launch
+  int32_t chain;
+  int32_t chain_min_n;  // only children of at least this many vertices are chained
 };
 
 // ---------------------------------------------------------------- device helpers

@@ -54,6 +54,8 @@ struct Sh {
   unsigned long long redu[NW_MAX + 1];
   unsigned long long hsum;
   int vi[8];
+  ItemDesc keep;  // chained form: the child this workgroup processes next
+  int has_keep;
 };
 
 struct St {
@@ -71,6 +73,51 @@ struct St {
   bool pf;                     // accumulate this item's phase profile
   unsigned long long *prof_cnt; // sub-phase timing slots (profiling runs only)
 };
+
+// Pointers that say which memory they address.  The phases are separate functions shared
+// by every placement, so a pointer they receive is generic; rebuilding it from its LDS
+// offset (low 32 bits) or as a global address lets the compiler emit LDS (ds_*) or
+// global (global_*) instructions instead of flat ones.  (A plain cast to the LDS address
+// space and back is folded away, hence the integer round trip.)
+template <typename T>
+DEV T *as_lds(T *p) {
+  return (T *)(__attribute__((address_space(3))) T *)(uintptr_t)(uint32_t)(uintptr_t)p;
+}
+template <typename T>
+DEV T *as_glb(T *p) {
+  return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+// The item state with every pointer typed for its placement: LDS = scan arrays (A, B, D,
+// E, R, bitmaps) in LDS, CL = super-vertex ids C in LDS; the optional mark bits and 16-bit
+// adjacency are LDS arrays when present.
+template <bool LDS, bool CL>
+DEV St typed_st(const St &in) {
+  St s = in;
+  s.F = as_glb(s.F);
+  s.adjg = as_glb(s.adjg);
+  s.mark = as_glb(s.mark);
+  s.lists = as_glb(s.lists);
+  if constexpr (LDS) {
+    s.A = as_lds(s.A);
+    s.B = as_lds(s.B);
+    s.D = as_lds(s.D);
+    s.E = as_lds(s.E);
+    s.R = as_lds(s.R);
+    s.bits = as_lds(s.bits);
+    s.markbits = s.markbits ? as_lds(s.markbits) : nullptr;
+    s.adj16 = s.adj16 ? as_lds(s.adj16) : nullptr;
+  } else {
+    s.A = as_glb(s.A);
+    s.B = as_glb(s.B);
+    s.D = as_glb(s.D);
+    s.E = as_glb(s.E);
+    s.R = as_glb(s.R);
+    s.bits = as_glb(s.bits);
+  }
+  if constexpr (CL) s.C = as_lds(s.C);
+  else s.C = as_glb(s.C);
+  return s;
+}
 
 DEV int row_end(const St &s, int x) { return x + 1 < s.n ? ldr(&s.R[x + 1]) : s.m; }
 
@@ -390,8 +437,10 @@ DEV void err(const ItemArgs &A, int code) {
 // one tree; c = the root with the most members.  Then every edge is united from the side
 // of an endpoint that is not (yet) a child of c; an edge skipped from both sides joins two
 // members of c's tree, so the components are exact.  Rows of c's members are not read.
-NOINL int item_cc(const St &s_in, bool use_deg, int kmin, Sh &sh) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
+template <bool LDS, bool CL>
+NOINL int item_cc(const St &s_in, bool use_deg, int kmin, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += ib()) {
@@ -460,10 +509,16 @@ NOINL int item_cc(const St &s_in, bool use_deg, int kmin, Sh &sh) {
 // are compacted into the other arena inside [b, b+n) / [eb, eb+m) and pushed.
 // Uses A (sizes), D (child starts), E (new positions), C (row offsets by new position)
 // and F (write cursors by new position).
-NOINL void item_rebuild(const ItemArgs &A, const St &s_in, const ItemDesc &d, int gate, Sh &sh) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
-  const Arena &ar = A.ar[d.depth & 1];
-  const Arena &nx = A.ar[(d.depth + 1) & 1];
+template <bool LDS, bool CL>
+NOINL void item_rebuild(const ItemArgs &A, const St &s_in, const ItemDesc &d, int gate, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
+  Arena ar = A.ar[d.depth & 1], nx = A.ar[(d.depth + 1) & 1];
+  ar.vtx = as_glb(ar.vtx);
+  nx.vtx = as_glb(nx.vtx);
+  nx.rs = as_glb(nx.rs);
+  nx.rd = as_glb(nx.rd);
+  nx.adj = as_glb(nx.adj);
   int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += ib()) st(&s.A[i], 0);
@@ -577,12 +632,40 @@ NOINL void item_rebuild(const ItemArgs &A, const St &s_in, const ItemDesc &d, in
     c.flags = 0;
     return c;
   };
+  // chained form: the workgroup keeps its largest child (the smallest start among equal
+  // sizes) and processes it next, without waiting for the level to end, when the child has
+  // at least chain_min_n vertices (the long chains of nested splits) and belongs to this
+  // launch's size bin: a large-bin workgroup keeps large children only (small ones run
+  // several to a CU in the small bin), a small-bin workgroup keeps children whose scan
+  // state fits its LDS; the other children go to the lists
+  int keep = -1;
+  if (A.chain) {
+    unsigned long long best = 0;
+    for (int i = threadIdx.x; i < n; i += ib())
+      if (ldr(&s.B[i]) == i) {
+        unsigned long long v = ((unsigned long long)(uint32_t)ldr(&s.A[i]) << 32) | (uint32_t)(0x7fffffff - i);
+        best = v > best ? v : best;
+      }
+    best = ~block_min_u64<IB_MAX>(~best, sh.redu);
+    if (best) {
+      int i = 0x7fffffff - (int)(best & 0xffffffffu);
+      ItemDesc c = child(i);
+      int ccap = (int)wcc_k_of(A.crit, c.n, A.lin_num, A.lin_den);
+      int64_t need = item_state_words(c.n, c.m, ccap);
+      bool big_bin = A.lds_words > A.small_words;
+      if (c.n >= A.chain_min_n && (big_bin ? need > A.small_words : (need <= A.lds_words || A.gbits_words > 0)))
+        keep = i;
+    }
+  }
   for (int i = threadIdx.x; i < n; i += ib()) {
     if (ldr(&s.B[i]) != i) continue;
     ItemDesc c = child(i);
     atomicAdd(&A.cnt[CNT_ALG_BYTES], (unsigned long long)(16LL * c.n + 4LL * c.m));
     int ccap = (int)wcc_k_of(A.crit, c.n, A.lin_num, A.lin_den);
-    if (A.out_big && item_state_words(c.n, c.m, ccap) > A.small_words) {
+    if (i == keep) {
+      sh.keep = c;
+      sh.has_keep = 1;
+    } else if (A.out_big && item_state_words(c.n, c.m, ccap) > A.small_words) {
       int slot = atomicAdd(A.out_big_count, 1);
       if (slot < A.out_big_cap) A.out_big[slot] = c;
       else err(A, WCC_ENOMEM);
@@ -634,9 +717,12 @@ DEV int block_suffix_min(int v, int carry, Sh &sh, int *chunk_min) {
   return x < later ? x : later;
 }
 
-NOINL int item_leaf_peel(const ItemArgs &A, const St &s_in, const ItemDesc &d, Sh &sh) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
-  const Arena &ar = A.ar[d.depth & 1];
+template <bool LDS, bool CL>
+NOINL int item_leaf_peel(const ItemArgs &A, const St &s_in, const ItemDesc &d, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
+  Arena ar = A.ar[d.depth & 1];
+  ar.vtx = as_glb(ar.vtx);
   const int n = s.n;
   // a tree keeps its largest vertex (it is the last one standing)
   const int pin = (long long)s.m == 2LL * (n - 1) ? n - 1 : -1;
@@ -754,8 +840,10 @@ NOINL int item_leaf_peel(const ItemArgs &A, const St &s_in, const ItemDesc &d, S
 // ---------------------------------------------------------------- k-core peel
 // A[i] ends as i's degree inside the surviving core (alive iff A[i] >= k).
 // Returns the number of removed vertices.  D and E hold the frontiers.
-NOINL int item_peel(const St &s_in, int k, Sh &sh) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
+template <bool LDS, bool CL>
+NOINL int item_peel(const St &s_in, int k, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   int n = s.n;
   if (threadIdx.x == 0) sh.vi[0] = 0;
   __syncthreads();
@@ -962,8 +1050,10 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
 // which most edges join one tree and stop at a single comparison.  Uses B (union-find) and the
 // entry marks (used edges); returns false as soon as a forest does not span (the greedy
 // choice can fail even when lambda >= t: the caller then runs the scans).
-NOINL bool forest_certificate(const St &s_in, int t, Sh &sh) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
+template <bool LDS, bool CL>
+NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   const int n = s.n;
   unsigned long long q = s.pf ? wall_clock64() : 0;
   mark_clear(s, s.m);
@@ -1008,9 +1098,10 @@ NOINL bool forest_certificate(const St &s_in, int t, Sh &sh) {
 // arrays an LDS-state item holds in LDS), every vertex first links up to two sampled edges
 // per forest, and then every unused edge joins the first forest whose trees it connects.
 // One pass over the edges instead of t, but no early stop when a forest cannot span.
-template <int TMAX>
-NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
+template <int TMAX, bool LDS, bool CL>
+NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   const int n = s.n;
   auto P = [&](int f) -> int32_t * {
     return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : f == 3 ? s.E : f == 4 ? s.C : s.F;
@@ -1030,7 +1121,7 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh) {
     int r0 = ldr(&s.R[x]), dg = row_end(s, x) - r0;
 #pragma unroll
     for (int f = 0; f < TMAX; f++) {
-      if (f >= t) break;
+      if (f >= t) continue;
       // two entries of x's row, at a different place for every forest
       int e1 = r0 + (2 * f) % dg, e2 = r0 + (2 * f + 1) % dg;
       int y1 = adj_at(s, e1), y2 = adj_at(s, e2);
@@ -1055,13 +1146,16 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh) {
   sub_mark(s, 20, &q);
   for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
     if (y <= x || mark_get(s, e)) return;
+    // (no early exit from the unrolled loop: constant indices keep links[] in registers)
+    bool done = false;
 #pragma unroll
     for (int f = 0; f < TMAX; f++) {
-      if (f >= t) break;
-      int32_t *Pf = P(f);
-      if (ld(&Pf[x]) != ld(&Pf[y]) && uf_link(Pf, x, y)) {
-        links[f]++;
-        break;
+      if (!done && f < t) {
+        int32_t *Pf = P(f);
+        if (ld(&Pf[x]) != ld(&Pf[y]) && uf_link(Pf, x, y)) {
+          links[f]++;
+          done = true;
+        }
       }
     }
   });
@@ -1076,10 +1170,11 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh) {
 }
 
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
-template <bool LDS>
-NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int cap, Sh &sh,
+template <bool LDS, bool CL>
+NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int cap, Sh &sh_in,
                     long long *steps_out, long long *rounds_out) {
-  const St s = s_in;  // (a local copy: its fields stay in registers)
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   int n = s.n;
   unsigned long long pt = s.pf ? wall_clock64() : 0;
   // Phase 0: minimum degree and its smallest vertex
@@ -1102,7 +1197,8 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
   // checking every forest per edge, most of all when the union-finds are in global memory)
   constexpr int TONE = 4;
   if (bound > 1 && (long long)s.m / 2 >= (long long)bound * (n - 1) &&
-      (bound <= TONE ? forest_certificate_one<TONE>(s_in, bound, sh) : forest_certificate(s_in, bound, sh))) {
+      (bound <= TONE ? forest_certificate_one<TONE, LDS, CL>(s_in, bound, sh)
+                      : forest_certificate<LDS, CL>(s_in, bound, sh))) {
     if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
     bound = -bound;  // (certified; restored below)
   }
@@ -1370,14 +1466,14 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
 
   if (A.ccr_out) {
     // components of the cluster's induced subgraph (Alg. 1), labelled by smallest member
-    item_cc(s, false, 0, sh);
+    item_cc<LDS, CL>(s, false, 0, sh);
     for (int i = threadIdx.x; i < n; i += ib()) A.ccr_out[ar.vtx[d.b + i]] = ar.vtx[d.b + ld(&s.B[i])];
     __syncthreads();
     return;
   }
   if (A.split_only) {
     // mincut_split: disconnected -> 0 and the component of the first vertex
-    int nc = item_cc(s, false, 0, sh);
+    int nc = item_cc<LDS, CL>(s, false, 0, sh);
     int lam;
     if (n < 2) {
       lam = 0;
@@ -1388,7 +1484,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
       for (int i = threadIdx.x; i < n; i += ib()) st(&s.F[i], (int32_t)(ld(&s.B[i]) == 0));
       __syncthreads();
     } else {
-      lam = item_mincut<LDS>(A, s, d, cap, sh, &steps, &rounds);
+      lam = item_mincut<LDS, CL>(A, s, d, cap, sh, &steps, &rounds);
     }
     int64_t p0 = A.split_pos[set];
     for (int i = threadIdx.x; i < n; i += ib()) A.split_side[p0 + i] = (uint8_t)ld(&s.F[i]);
@@ -1403,10 +1499,10 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   }
 
   if (d.flags & ITEM_CCR) {
-    int nc = item_cc(s, false, 0, sh);
+    int nc = item_cc<LDS, CL>(s, false, 0, sh);
     ph_mark(A, s, 0, &pt);
     if (nc > 1) {
-      item_rebuild(A, s, d, A.s_pre, sh);
+      item_rebuild<LDS, CL>(A, s, d, A.s_pre, sh);
       ph_mark(A, s, 9, &pt);
       return;
     }
@@ -1414,12 +1510,12 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   }
   if (threadIdx.x == 0) atomicAdd(&A.cnt[CNT_ITEMS], 1ull);
   if (A.mode == WCC_PRUNE_KCORE) {
-    int removed = item_peel(s, k, sh);
+    int removed = item_peel<LDS, CL>(s, k, sh);
     ph_mark(A, s, 1, &pt);
     if (removed > 0) {
       if (removed < n) {
-        item_cc(s, true, k, sh);
-        item_rebuild(A, s, d, A.s_post, sh);
+        item_cc<LDS, CL>(s, true, k, sh);
+        item_rebuild<LDS, CL>(A, s, d, A.s_post, sh);
       }
       ph_mark(A, s, 2, &pt);
       return;
@@ -1435,12 +1531,12 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     }
     dmin = (int)block_min_u64<IB_MAX>((unsigned long long)(uint32_t)dmin, sh.redu);
     if (dmin == 1) {
-      if (item_leaf_peel(A, s, d, sh) > 0) item_rebuild(A, s, d, A.s_post, sh);
+      if (item_leaf_peel<LDS, CL>(A, s, d, sh) > 0) item_rebuild<LDS, CL>(A, s, d, A.s_post, sh);
       ph_mark(A, s, 9, &pt);
       return;
     }
   }
-  int lam = item_mincut<LDS>(A, s, d, k, sh, &steps, &rounds);
+  int lam = item_mincut<LDS, CL>(A, s, d, k, sh, &steps, &rounds);
   pt = s.pf ? wall_clock64() : 0;
   // record: |S| and the order-free hash of S's global ids
   int ss = 0;
@@ -1494,7 +1590,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   for (int i = threadIdx.x; i < n; i += ib()) st(&s.B[i], ld(&s.F[i]) ? (int)mS : (int)mC);
   __syncthreads();
   ph_mark(A, s, 8, &pt);
-  item_rebuild(A, s, d, A.s_post, sh);
+  item_rebuild<LDS, CL>(A, s, d, A.s_post, sh);
   ph_mark(A, s, 9, &pt);
 }
 
@@ -1521,13 +1617,20 @@ __global__ void __launch_bounds__(IB_MAX) k_items(ItemArgs A) {
     int c = *A.nitems_dev;
     nit = c < nit ? c : nit;
   }
+  if (threadIdx.x == 0) sh.has_keep = 0;
+  __syncthreads();
   for (;;) {
-    if (threadIdx.x == 0) cur = atomicAdd(A.next, 1);
+    // a child kept by the previous item first (chained form), else the next list item
+    if (threadIdx.x == 0) cur = sh.has_keep ? -1 : atomicAdd(A.next, 1);
     __syncthreads();
     int it = cur;
+    ItemDesc d;
+    if (it < 0) d = sh.keep;
+    else if (it < nit) d = A.items[it];
     __syncthreads();
     if (it >= nit) break;
-    ItemDesc d = A.items[it];
+    if (threadIdx.x == 0) sh.has_keep = 0;
+    __syncthreads();
     process_item(A, d, dyn, it, sh);
     __syncthreads();
   }

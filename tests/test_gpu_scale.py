@@ -144,6 +144,34 @@ def test_mid_size_clusters(mode, crit):
         assert int(wrec["n"].max()) > 16384
 
 
+def test_c2_paper_mode_sampled():
+    """PAPER mode (Alg. 1-3 as printed, no pruning) on whole clusters of the 10M-vertex
+    workload up to 20,000 vertices: the oracle removes vertices of low degree one split
+    at a time, so its run time limits the sample (the whole workload takes it well over
+    ten minutes on 8 threads)."""
+    import paper_2509_02590_amd as w
+    g, o, a, m = _workload("c2")
+    memb = g.membership
+    sizes = np.bincount(memb[memb >= 0])
+    rng = np.random.default_rng(33)
+    ids = np.nonzero(sizes > 0)[0]
+    small = ids[sizes[ids] <= 3000]
+    mid = ids[(sizes[ids] > 3000) & (sizes[ids] <= 20000)]
+    pick = np.concatenate([rng.choice(small, 300, replace=False), rng.choice(mid, 4, replace=False)])
+    memb_s = np.where(np.isin(memb, pick), memb, -1).astype(np.int32)
+    t0 = time.time()
+    want, wrec = oracle.wcc(g.offsets, g.indices, memb_s, mode="paper", nthreads=_threads())
+    print("oracle paper on %d sampled clusters: %.1f s, %d records" % (len(pick), time.time() - t0, len(wrec)),
+          flush=True)
+    ms = torch.from_numpy(memb_s).to(m.device)
+    for exec_mode in ("plain", "batched"):
+        got, st, rec = w.wcc_run(o, a, ms, mode="paper", exec_mode=exec_mode, graph=False, records_cap=4_000_000)
+        got = got.cpu().numpy()
+        print("gpu paper %s: %.0f ms, %d levels" % (exec_mode, st.ms_total, st.levels), flush=True)
+        assert np.array_equal(got, want), (exec_mode, int((got != want).sum()))
+        assert _rec_key(rec) == _rec_key(wrec), exec_mode
+
+
 def _sample_clusters(memb, seed, n_small=400, n_mid=6, n_top=3):
     """Random small and mid-size clusters plus the n_top largest ones."""
     sizes = np.bincount(memb[memb >= 0])
