@@ -406,6 +406,8 @@ Shape exec_shape(const Workspace &w) {
   return sh;
 }
 
+void print_phases(const unsigned long long *ph);
+
 int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, const wcc_params &p,
                int64_t *levels, double *ms_kernel, int64_t *launches, hipStream_t s) {
   Shape shp = exec_shape(w);
@@ -469,6 +471,8 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       Bg.nitems = nbig;
       Bg.next = dnext_big;
       Bg.lds_words = (int32_t)(big_bytes / 4);
+      if (base.prof == 3) Bg.prof = 2;  // profile: the largest item of each level only
+      if (base.prof == 4) Bg.prof = 0;  // profile: the small-bin items only
       HIP_TRY(hipEventRecord(w.evb0, s));
       TRY(items_launch(Bg, grid_big, big_bytes, s));
       HIP_TRY(hipEventRecord(w.evb1, s));
@@ -481,6 +485,8 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       Sm.lds_words = (int32_t)(lds_bytes / 4);
       Sm.gbits_words = 0;  // (small-bin items keep their scan state in LDS)
       if (base.split_only) Sm.split_set = set_sorted + nbig;
+      if (base.prof == 3) Sm.prof = nbig > 0 ? 0 : 2;
+      if (base.prof == 4) Sm.prof = 1;
       HIP_TRY(hipStreamWaitEvent(w.s2, w.evf, 0));
       HIP_TRY(hipEventRecord(w.evs0, w.s2));
       TRY(items_launch(Sm, grid_small, lds_bytes, w.s2));
@@ -503,9 +509,19 @@ int run_levels(Workspace &w, ItemArgs base, int32_t nitems0, int max_cap_crit, c
       (*launches)++;
     }
     (*levels)++;
-    if (env_int("WCC_VERBOSE", 0))
-      fprintf(stderr, "[wcc] level %lld: %d items (%d large, largest n=%d) -> %d children; large bin %.2f ms, "
-              "small bin %.2f ms\n", (long long)*levels, nitems, nbig, top.n, nout, ms_b, ms_s);
+    if (env_int("WCC_VERBOSE", 0)) {
+      fprintf(stderr, "[wcc] level %lld: %d items (%d large, largest n=%d m=%lld) -> %d children; large bin "
+              "%.2f ms, small bin %.2f ms\n", (long long)*levels, nitems, nbig, top.n, (long long)top.m, nout, ms_b,
+              ms_s);
+      if (base.prof) {
+        // this level's phase totals, then cleared for the next level
+        unsigned long long ph[CNT_PH_END - CNT_PH];
+        HIP_TRY(hipMemcpyAsync(ph, base.cnt + CNT_PH, sizeof(ph), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        print_phases(ph);
+        TRY(prim_fill32((uint32_t *)(base.cnt + CNT_PH), 0u, 2 * (CNT_PH_END - CNT_PH), s));
+      }
+    }
     if (nout > A.out_cap) return WCC_ENOMEM;
     long long errc = 0;
     HIP_TRY(hipMemcpyAsync(&errc, base.cnt + CNT_ERR, sizeof(errc), hipMemcpyDeviceToHost, s));
@@ -775,6 +791,22 @@ int ensure_items(Workspace &w, int64_t cap, bool with_sets) {
   return WCC_OK;
 }
 
+// Prints the per-phase clock totals (CNT_PH slots; the wall clock runs at 100 MHz).
+void print_phases(const unsigned long long *ph) {
+  static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
+                                "lists", "degree", "record", "split-rebuild", "steps", "certified", "rounds"};
+  fprintf(stderr, "[wcc phase ms, summed over workgroups]");
+  for (int i = 0; i < 13; i++)
+    fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)ph[i] : ph[i] / 1e5);
+  fprintf(stderr, "\n[wcc cc ms] sample=%.2f compress=%.2f pick=%.2f; certificate: sample=%.2f compress=%.2f pass=%.2f\n",
+          ph[16] / 1e5, ph[17] / 1e5, ph[18] / 1e5, ph[19] / 1e5, ph[20] / 1e5, ph[21] / 1e5);
+  fprintf(stderr, "[wcc sub-phases ms] forest=%.2f unions=%.2f finds=%.2f relabel=%.2f lists-count=%.2f "
+          "lists-scan=%.2f lists-fill=%.2f cc-unite=%.2f cc-roots=%.2f rebuild-head=%.2f "
+          "rebuild-degrees=%.2f rebuild-offsets=%.2f rebuild-fill=%.2f\n",
+          ph[22] / 1e5, ph[23] / 1e5, ph[24] / 1e5, ph[25] / 1e5, ph[26] / 1e5, ph[27] / 1e5, ph[28] / 1e5,
+          ph[29] / 1e5, ph[30] / 1e5, ph[31] / 1e5, ph[13] / 1e5, ph[15] / 1e5, ph[14] / 1e5);
+}
+
 // Reads the device counters of a finished run into stats (and the record count).
 int collect_counts(Workspace &w, wcc_stats *st, int64_t *nrec, bool prof, hipStream_t s) {
   unsigned long long hc[CNT_NUM];
@@ -793,22 +825,7 @@ int collect_counts(Workspace &w, wcc_stats *st, int64_t *nrec, bool prof, hipStr
   st->scan_rounds = (int64_t)hc[CNT_ROUNDS];
   st->item_alg_bytes = (int64_t)hc[CNT_ALG_BYTES];
   if (nrec) *nrec = (int64_t)hc[CNT_RECORDS];
-  if (prof) {
-    static const char *names[] = {"ccr-cc", "peel", "prune-children", "cut-setup", "scan", "contract",
-                                  "lists", "degree", "record", "split-rebuild", "steps", "certified", "rounds"};
-    fprintf(stderr, "[wcc phase ms, summed over workgroups]");
-    for (int i = 0; i < 13; i++)
-      if (names[i][0])
-        fprintf(stderr, " %s=%.2f", names[i], i >= 10 ? (double)hc[CNT_PH + i] : hc[CNT_PH + i] / 1e5);
-    fprintf(stderr, "\n[wcc cc ms] sample=%.2f compress=%.2f pick=%.2f; certificate: sample=%.2f compress=%.2f pass=%.2f\n",
-            hc[CNT_PH + 16] / 1e5, hc[CNT_PH + 17] / 1e5, hc[CNT_PH + 18] / 1e5, hc[CNT_PH + 19] / 1e5,
-            hc[CNT_PH + 20] / 1e5, hc[CNT_PH + 21] / 1e5);
-    fprintf(stderr, "[wcc sub-phases ms] forest=%.2f unions=%.2f finds=%.2f relabel=%.2f lists-count=%.2f "
-            "lists-scan=%.2f lists-fill=%.2f cc-unite=%.2f cc-roots=%.2f rebuild-head=%.2f\n",
-            hc[CNT_PH + 22] / 1e5, hc[CNT_PH + 23] / 1e5, hc[CNT_PH + 24] / 1e5, hc[CNT_PH + 25] / 1e5,
-            hc[CNT_PH + 26] / 1e5, hc[CNT_PH + 27] / 1e5, hc[CNT_PH + 28] / 1e5, hc[CNT_PH + 29] / 1e5,
-            hc[CNT_PH + 30] / 1e5, hc[CNT_PH + 31] / 1e5);
-  }
+  if (prof) print_phases(hc + CNT_PH);
   return WCC_OK;
 }
 

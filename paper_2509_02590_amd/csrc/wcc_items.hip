@@ -47,6 +47,8 @@ constexpr int IB_MAX = 512;
 constexpr int NW_MAX = IB_MAX / 64;
 DEV int ib() { return (int)blockDim.x; }
 constexpr int CH = 16;   // entries per thread per chunk in entry-parallel passes
+constexpr int RV = 8;    // vertices per thread per round in the rebuild's vertex passes
+constexpr int NPACK = 4; // children placed by one packed block scan in the rebuild
 
 struct Sh {
   int red[NW_MAX + 1];
@@ -54,6 +56,8 @@ struct Sh {
   unsigned long long redu[NW_MAX + 1];
   unsigned long long hsum;
   int vi[8];
+  int crep[NPACK], cstart[NPACK];  // rebuild: first children's representatives and starts
+  int own_lo;                       // entry_rounds: first row of the next round
   ItemDesc keep;  // chained form: the child this workgroup processes next
   int has_keep;
 };
@@ -62,11 +66,13 @@ struct St {
   int32_t *A, *B, *D, *E, *R;  // LDS or global
   int32_t *C, *F;              // global
   uint64_t *bits;              // LDS or global
+  uint64_t *bits1;             // LDS summary levels of global-state items, or nullptr (in bits)
   uint16_t *adj16;             // LDS copy of the item's adjacency, or nullptr
   const int32_t *adjg;         // the item's adjacency in the arena (entry 0 = eb)
   uint8_t *mark;               // global, entry-indexed contraction marks (if no markbits)
   uint32_t *markbits;          // LDS bit array of contraction marks, or nullptr
   int32_t *lists;              // global, entry-indexed crossing lists (rounds >= 2)
+  int32_t *own;                // LDS, ib() words: chunk owners of entry rounds, or nullptr
   int n, m;
   int nw0, nw1, nw2, ls;       // bitmap geometry per level
   bool l1;                     // summary level of the bitmaps kept (large items only)
@@ -97,6 +103,8 @@ DEV St typed_st(const St &in) {
   s.adjg = as_glb(s.adjg);
   s.mark = as_glb(s.mark);
   s.lists = as_glb(s.lists);
+  s.own = s.own ? as_lds(s.own) : nullptr;
+  s.bits1 = s.bits1 ? as_lds(s.bits1) : nullptr;
   if constexpr (LDS) {
     s.A = as_lds(s.A);
     s.B = as_lds(s.B);
@@ -205,22 +213,59 @@ DEV void count_agg(int32_t *a, int key, bool act) {
   if ((int)__lane_id() == leader) atomicAdd(&a[k0], (int)__popcll(same));
 }
 
+// Calls body(base, x) for every thread's chunk of CH consecutive entries [base, base + CH)
+// of lists stored in ascending owner order (owner x covers [start[x], end(x)), end(x) =
+// start[x+1], or total for the last), x = the owner of entry base.  The chunks of one
+// round, ib() * CH entries, belong to the threads in order.  With s.own (an LDS array of
+// ib() words; items whose state is in global memory) the rows reaching into a round are
+// read by the threads together (consecutive rows, one round trip for most rounds) and
+// write the owner of every chunk start they hold into s.own; the row of the round's last
+// entry is where the next round's rows begin.  Otherwise each thread finds its owner by
+// binary search.  With s.own the call contains barriers: the whole block must make it.
+template <typename B>
+DEV void entry_rounds(const St &s, Sh &sh, const int32_t *start, int n, int total, B body) {
+  if (s.own) {
+    int lo = 0;
+    for (int blk = 0; blk < total; blk += ib() * CH) {
+      const int bend = blk + ib() * CH < total ? blk + ib() * CH : total;
+      for (int r = lo + (int)threadIdx.x; r < n; r += ib()) {
+        int r0 = ldr(&start[r]);
+        if (r0 >= bend) break;
+        int r1 = r + 1 < n ? ldr(&start[r + 1]) : total;
+        int a = r0 > blk ? r0 : blk, b = r1 < bend ? r1 : bend;
+        if (a < b) {
+          for (int c = (a - blk + CH - 1) / CH; c < (b - blk + CH - 1) / CH; c++) s.own[c] = r;
+          if (b == bend) sh.own_lo = r;
+        }
+      }
+      __syncthreads();
+      const int base = blk + (int)threadIdx.x * CH;
+      const int x = base < total ? s.own[threadIdx.x] : 0;
+      lo = sh.own_lo;
+      __syncthreads();
+      if (base < total) body(base, x);
+    }
+  } else {
+    for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
+      int lo = 0, hi = n - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (ldr(&start[mid]) <= base) lo = mid;
+        else hi = mid - 1;
+      }
+      body(base, lo);
+    }
+  }
+}
+
 // Calls f(x, e, y) for every entry e in [0, total) of lists stored in ascending owner
-// order: owner x covers [start[x], end(x)), end(x) = start[x+1] (or total for the last),
-// and y = get(e).  Each thread takes CH consecutive entries.
+// order, y = get(e) (entry_rounds' chunks).
 template <typename G, typename F>
-DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
-  for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
+DEV void for_entries(const St &s, Sh &sh, const int32_t *start, int n, int total, G get, F f) {
+  entry_rounds(s, sh, start, n, total, [&](int base, int x) {
     int yv[CH];
 #pragma unroll
     for (int i = 0; i < CH; i++) yv[i] = base + i < total ? get(base + i) : 0;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (ldr(&start[mid]) <= base) lo = mid;
-      else hi = mid - 1;
-    }
-    int x = lo;
     int xend = x + 1 < n ? ldr(&start[x + 1]) : total;
 #pragma unroll
     for (int i = 0; i < CH; i++) {
@@ -233,21 +278,14 @@ DEV void for_entries(const int32_t *start, int n, int total, G get, F f) {
         f(x, e, yv[i]);
       }
     }
-  }
+  });
 }
 
 // for_entries that leaves out the entries of owners x with skip(x): a chunk that lies
-// inside one skipped row is passed over without loading it.
+// inside skipped rows only is passed over without loading it.
 template <typename S, typename G, typename F>
-DEV void for_entries_skip(const int32_t *start, int n, int total, S skip, G get, F f) {
-  for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (ldr(&start[mid]) <= base) lo = mid;
-      else hi = mid - 1;
-    }
-    int x = lo;
+DEV void for_entries_skip(const St &s, Sh &sh, const int32_t *start, int n, int total, S skip, G get, F f) {
+  entry_rounds(s, sh, start, n, total, [&](int base, int x) {
     int xend = x + 1 < n ? ldr(&start[x + 1]) : total;
     bool sk = skip(x);
     // the chunk is passed over when every owner it touches is skipped
@@ -257,7 +295,7 @@ DEV void for_entries_skip(const int32_t *start, int n, int total, S skip, G get,
       zend = z + 1 < n ? ldr(&start[z + 1]) : total;
       all = skip(z);
     }
-    if (all) continue;
+    if (all) return;
     int yv[CH];
 #pragma unroll
     for (int i = 0; i < CH; i++) yv[i] = base + i < total ? get(base + i) : 0;
@@ -273,24 +311,17 @@ DEV void for_entries_skip(const int32_t *start, int n, int total, S skip, G get,
         if (!sk) f(x, e, yv[i]);
       }
     }
-  }
+  });
 }
 
 // Calls f(x, e, y) for the marked entries e in [0, total) only (lists stored in ascending
 // owner order, as for for_entries); chunks without a mark are passed over unread.
 template <typename G, typename F>
-DEV void for_marked_entries(const St &s, const int32_t *start, int n, int total, G get, F f) {
+DEV void for_marked_entries(const St &s, Sh &sh, const int32_t *start, int n, int total, G get, F f) {
   static_assert(CH == 16, "mark_chunk reads 16 entries");
-  for (int base = threadIdx.x * CH; base < total; base += ib() * CH) {
+  entry_rounds(s, sh, start, n, total, [&](int base, int x) {
     uint32_t mk = mark_chunk(s, base, total);
-    if (!mk) continue;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (ldr(&start[mid]) <= base) lo = mid;
-      else hi = mid - 1;
-    }
-    int x = lo;
+    if (!mk) return;
     int xend = x + 1 < n ? ldr(&start[x + 1]) : total;
     int yv[CH];
 #pragma unroll
@@ -305,20 +336,26 @@ DEV void for_marked_entries(const St &s, const int32_t *start, int n, int total,
       }
       f(x, e, yv[i]);
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------- bitmap levels
 // (level j < 64 and ls < 2^24: a 24-bit multiply)
 DEV uint64_t *lvl0(const St &s, int j) { return s.bits + __umul24((unsigned)j, (unsigned)s.ls); }
-DEV uint64_t *lvl1(const St &s, int j) { return s.bits + __umul24((unsigned)j, (unsigned)s.ls) + s.nw0; }
+// GL (items whose state is in global memory): the summary levels are the LDS array bits1
+template <bool GL>
+DEV uint64_t *lvl1(const St &s, int j) {
+  if constexpr (GL) return s.bits1 + __umul24((unsigned)j, (unsigned)s.nw1);
+  else return s.bits + __umul24((unsigned)j, (unsigned)s.ls) + s.nw0;
+}
 
 // Level j: a bit per vertex (L0) and, for large items, a summary bit per L0 word (L1)
 // that is set whenever a bit of that word is set but only cleared lazily.  Setting and
 // clearing need no returned values, so they never stall the scan.
+template <bool GL>
 DEV void bit_set(const St &s, int j, int y) {
   atomicOr((unsigned long long *)&lvl0(s, j)[y >> 6], 1ull << (y & 63));
-  if (s.l1) atomicOr((unsigned long long *)&lvl1(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
+  if (s.l1) atomicOr((unsigned long long *)&lvl1<GL>(s, j)[y >> 12], 1ull << ((y >> 6) & 63));
 }
 
 DEV void bit_clear(const St &s, int j, int x) {
@@ -333,9 +370,10 @@ DEV uint64_t readlane64(uint64_t v, int l) {
 // Wavefront-cooperative search of level j: its smallest member, -1 when it is empty, -2
 // on an inconsistent bitmap.  All lanes return it.  Summary words whose L0 words all
 // turned empty are reset.
+template <bool GL>
 DEV int level_first(const St &s, int j) {
   const int lane = __lane_id();
-  uint64_t *L1 = lvl1(s, j);
+  uint64_t *L1 = lvl1<GL>(s, j);
   const uint64_t *L0 = lvl0(s, j);
   if (!s.l1) {
     // small items keep no summary: a wavefront reads 64 L0 words at a time
@@ -376,9 +414,10 @@ DEV int level_first(const St &s, int j) {
 // The smallest id in the highest non-empty level, searching down from *j (every level
 // above *j is empty); -1 when every super-vertex is scanned, -2 on an inconsistency.
 // *j receives the level found.
+template <bool GL>
 DEV int bit_pick(const St &s, int *j) {
   for (int l = *j; l >= 0; l--) {
-    int x = level_first(s, l);
+    int x = level_first<GL>(s, l);
     if (x != -1) {
       *j = l;
       return x;
@@ -415,7 +454,7 @@ DEV void ph_mark(const ItemArgs &A, const St &s, int ph, unsigned long long *t) 
   *t = now;
 }
 
-// sub-phase profile: thread 0 adds the time since *t to CNT_PH slot `slot` (22..31)
+// sub-phase profile: thread 0 adds the time since *t to CNT_PH slot `slot` (13..15, 16..31)
 DEV void sub_mark(const St &s, int slot, unsigned long long *t) {
   if (!s.pf || threadIdx.x != 0) return;
   unsigned long long now = wall_clock64();
@@ -485,7 +524,7 @@ NOINL int item_cc(const St &s_in, bool use_deg, int kmin, Sh &sh_in) {
   const int cs = best == ~0ull ? -1 : (int)(best & 0xffffffffu);
   sub_mark(s, 18, &q);
   for_entries_skip(
-      s.R, n, s.m, [&](int x) { int b = ld(&s.B[x]); return b < 0 || b == cs; },
+      s, sh, s.R, n, s.m, [&](int x) { int b = ld(&s.B[x]); return b < 0 || b == cs; },
       [&](int e) { return adj_at(s, e); },
       [&](int i, int, int j) {
         if (ld(&s.B[j]) >= 0) uf_unite(s.B, i, j);
@@ -523,100 +562,266 @@ NOINL void item_rebuild(const ItemArgs &A, const St &s_in, const ItemDesc &d, in
   unsigned long long q = s.pf ? wall_clock64() : 0;
   for (int i = threadIdx.x; i < n; i += ib()) st(&s.A[i], 0);
   __syncthreads();
-  for (int base = 0; base < n; base += ib()) {
-    int i = base + threadIdx.x;
-    int L = i < n ? ldr(&s.B[i]) : -1;
-    count_agg(s.A, L, L >= 0);
+  // child sizes by label (A), then labels of children of gate vertices or fewer dropped;
+  // RV vertices per thread and round, their loads issued together
+  for (int base = 0; base < n; base += ib() * RV) {
+    int L[RV];
+#pragma unroll
+    for (int k = 0; k < RV; k++) {
+      int i = base + k * ib() + threadIdx.x;
+      L[k] = i < n ? ldr(&s.B[i]) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < RV; k++) count_agg(s.A, L[k], L[k] >= 0);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += ib()) {
-    int L = ldr(&s.B[i]);
-    if (L >= 0 && ldr(&s.A[L]) <= gate) st(&s.B[i], -1);
+  for (int base = 0; base < n; base += ib() * RV) {
+    int L[RV], c[RV];
+#pragma unroll
+    for (int k = 0; k < RV; k++) {
+      int i = base + k * ib() + threadIdx.x;
+      L[k] = i < n ? ldr(&s.B[i]) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < RV; k++) c[k] = L[k] >= 0 ? ldr(&s.A[L[k]]) : gate + 1;
+#pragma unroll
+    for (int k = 0; k < RV; k++)
+      if (c[k] <= gate) st(&s.B[base + k * ib() + threadIdx.x], -1);
   }
   __syncthreads();
-  // child starts: exclusive scan over representatives
-  int carry = 0;
-  for (int base = 0; base < n; base += ib()) {
-    int i = base + threadIdx.x;
-    int v = 0;
-    if (i < n && ldr(&s.B[i]) == i) v = ldr(&s.A[i]);
-    int tot;
-    int pre = block_excl_scan<IB_MAX>(v, sh.red, &tot);
-    if (i < n) st(&s.D[i], carry + pre);
+  // child starts (D, by representative) and ordinals: one exclusive scan of
+  // (1 << 32) + size over the representatives, RV consecutive vertices per thread; the
+  // first NPACK children's representatives and starts are kept in sh
+  long long carry = 0;
+  for (int base = 0; base < n; base += ib() * RV) {
+    const int i0 = base + threadIdx.x * RV;
+    int sz[RV];
+    long long v = 0;
+#pragma unroll
+    for (int k = 0; k < RV; k++) {
+      int i = i0 + k;
+      sz[k] = (i < n && ldr(&s.B[i]) == i) ? ldr(&s.A[i]) : 0;
+      v += sz[k] ? (1LL << 32) + sz[k] : 0;
+    }
+    long long tot;
+    long long pre = carry + block_excl_scan64<IB_MAX>(v, sh.red64, &tot);
+#pragma unroll
+    for (int k = 0; k < RV; k++)
+      if (sz[k]) {
+        int start = (int)(pre & 0xffffffffLL), o = (int)(pre >> 32);
+        st(&s.D[i0 + k], start);
+        if (o < NPACK) {
+          sh.crep[o] = i0 + k;
+          sh.cstart[o] = start;
+        }
+        pre += (1LL << 32) + sz[k];
+      }
     carry += tot;
   }
-  int K = carry;
+  const int K = (int)(carry & 0xffffffffLL), NC = (int)(carry >> 32);
   __syncthreads();
   if (K == 0) return;
   sub_mark(s, 31, &q);
-  // stable new positions: wave 0 walks the item in order (E[i] = new position)
-  if (threadIdx.x < 64) {
-    for (int base = 0; base < n; base += 64) {
-      int i = base + threadIdx.x;
-      int L = i < n ? ldr(&s.B[i]) : -1;
-      uint64_t act = __ballot(L >= 0);
-      while (act) {
-        int leader = __ffsll((long long)act) - 1;
-        int LL = __shfl(L, leader, 64);
-        uint64_t peers = __ballot(L == LL) & act;
-        int pos0 = 0;
-        if ((int)threadIdx.x == leader) pos0 = atomicAdd(&s.D[LL], __popcll(peers));
-        pos0 = __shfl(pos0, leader, 64);
-        if (L == LL) st(&s.E[i], pos0 + __popcll(peers & lanemask_lt()));
-        act &= ~peers;
+  // stable new positions (E[i] = new position: the child's start plus the number of its
+  // vertices before i)
+  if (NC <= NPACK) {
+    // at most NPACK children: one block scan of NPACK 16-bit counters per round of
+    // ib() * RV consecutive vertices (at most 65535 of one child per round)
+    static_assert(NPACK * 16 <= 64 && IB_MAX * RV <= 65535, "packed child counters");
+    int crep[NPACK], cnext[NPACK];
+#pragma unroll
+    for (int c = 0; c < NPACK; c++) {
+      crep[c] = c < NC ? sh.crep[c] : -2;
+      cnext[c] = c < NC ? sh.cstart[c] : 0;
+    }
+    for (int base = 0; base < n; base += ib() * RV) {
+      const int i0 = base + threadIdx.x * RV;
+      int o[RV];
+      unsigned long long v = 0;
+#pragma unroll
+      for (int k = 0; k < RV; k++) {
+        int L = i0 + k < n ? ldr(&s.B[i0 + k]) : -1;
+        int c = -1;
+#pragma unroll
+        for (int cc = 0; cc < NPACK; cc++) c = L == crep[cc] ? cc : c;
+        o[k] = c;
+        if (c >= 0) v += 1ull << (16 * c);
+      }
+      long long tot;
+      unsigned long long pre = (unsigned long long)block_excl_scan64<IB_MAX>((long long)v, sh.red64, &tot);
+#pragma unroll
+      for (int k = 0; k < RV; k++)
+        if (o[k] >= 0) {
+          int c = o[k];
+          int b = c == 0 ? cnext[0] : c == 1 ? cnext[1] : c == 2 ? cnext[2] : cnext[3];
+          st(&s.E[i0 + k], b + (int)((pre >> (16 * c)) & 0xffffu));
+          pre += 1ull << (16 * c);
+        }
+#pragma unroll
+      for (int c = 0; c < NPACK; c++) cnext[c] += (int)(((unsigned long long)tot >> (16 * c)) & 0xffffu);
+    }
+    __syncthreads();
+  } else {
+    // more children: wave 0 walks the item in order with a cursor per child (D[L] ends
+    // at start + size and is restored after)
+    if (threadIdx.x < 64) {
+      for (int base = 0; base < n; base += 64) {
+        int i = base + threadIdx.x;
+        int L = i < n ? ldr(&s.B[i]) : -1;
+        uint64_t act = __ballot(L >= 0);
+        while (act) {
+          int leader = __ffsll((long long)act) - 1;
+          int LL = __shfl(L, leader, 64);
+          uint64_t peers = __ballot(L == LL) & act;
+          int pos0 = 0;
+          if ((int)threadIdx.x == leader) pos0 = atomicAdd(&s.D[LL], __popcll(peers));
+          pos0 = __shfl(pos0, leader, 64);
+          if (L == LL) st(&s.E[i], pos0 + __popcll(peers & lanemask_lt()));
+          act &= ~peers;
+        }
       }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += ib())
+      if (ldr(&s.B[i]) == i) st(&s.D[i], ldr(&s.D[i]) - ldr(&s.A[i]));
+  }
+  // clear new degrees and cursors
+  for (int i = threadIdx.x; i < K; i += ib()) {
+    st(&s.C[i], 0);
+    st(&s.F[i], 0);
   }
   __syncthreads();
-  // D[L] now holds start + size; restore starts; clear new degrees and cursors
-  for (int i = threadIdx.x; i < n; i += ib()) {
-    if (ldr(&s.B[i]) == i) st(&s.D[i], ldr(&s.D[i]) - ldr(&s.A[i]));
-    if (i < K) {
-      st(&s.C[i], 0);
-      st(&s.F[i], 0);
+  sub_mark(s, 31, &q);
+  // new degrees by new position (C): a thread's CH entries are read and their endpoints'
+  // labels gathered at once; one atomic per row run inside the chunk
+  entry_rounds(s, sh, s.R, n, s.m, [&](int base, int x) {
+    int yv[CH], by[CH];
+#pragma unroll
+    for (int i = 0; i < CH; i++) yv[i] = base + i < s.m ? s.adjg[base + i] : 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) by[i] = base + i < s.m ? ldr(&s.B[yv[i]]) : -2;
+    int xend = x + 1 < n ? ldr(&s.R[x + 1]) : s.m;
+    int Lx = ldr(&s.B[x]), cnt = 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) {
+      int e = base + i;
+      if (e < s.m) {
+        if (e >= xend) {
+          if (cnt) atomicAdd(&s.C[ldr(&s.E[x])], cnt);
+          cnt = 0;
+          do {
+            x++;
+            xend = x + 1 < n ? ldr(&s.R[x + 1]) : s.m;
+          } while (e >= xend);
+          Lx = ldr(&s.B[x]);
+        }
+        cnt += (Lx >= 0 && by[i] == Lx);
+      }
     }
-  }
-  __syncthreads();
-  // new degrees by new position (C); the rows are read from the arena
-  for_entries(s.R, n, s.m, [&](int e) { return s.adjg[e]; }, [&](int i, int, int j) {
-    int L = ldr(&s.B[i]);
-    if (L >= 0 && ldr(&s.B[j]) == L) atomicAdd(&s.C[ldr(&s.E[i])], 1);
+    if (cnt) atomicAdd(&s.C[ldr(&s.E[x])], cnt);
   });
   __syncthreads();
-  // row offsets by new position (exclusive scan of C, in place)
+  sub_mark(s, 13, &q);
+  // row offsets by new position (exclusive scan of C, in place; RV consecutive positions
+  // per thread)
   long long ecarry = 0;
-  for (int base = 0; base < K; base += ib()) {
-    int p = base + threadIdx.x;
-    long long v = p < K ? (long long)ldr(&s.C[p]) : 0;
+  for (int base = 0; base < K; base += ib() * RV) {
+    const int p0 = base + threadIdx.x * RV;
+    int c[RV];
+    long long v = 0;
+#pragma unroll
+    for (int k = 0; k < RV; k++) {
+      c[k] = p0 + k < K ? ldr(&s.C[p0 + k]) : 0;
+      v += c[k];
+    }
     long long tot;
-    long long pre = block_excl_scan64<IB_MAX>(v, sh.red64, &tot);
-    if (p < K) st(&s.C[p], (int)(ecarry + pre));
+    long long pre = ecarry + block_excl_scan64<IB_MAX>(v, sh.red64, &tot);
+#pragma unroll
+    for (int k = 0; k < RV; k++)
+      if (p0 + k < K) {
+        st(&s.C[p0 + k], (int)pre);
+        pre += c[k];
+      }
     ecarry += tot;
   }
   int M = (int)ecarry;
   __syncthreads();
   // vertex records of the children
-  for (int i = threadIdx.x; i < n; i += ib()) {
-    int L = ldr(&s.B[i]);
-    if (L < 0) continue;
-    int np = ldr(&s.E[i]);
-    int o = ldr(&s.C[np]);
-    int o1 = np + 1 < K ? ldr(&s.C[np + 1]) : M;
-    nx.vtx[d.b + np] = ar.vtx[d.b + i];
-    nx.rs[d.b + np] = d.eb + o;
-    nx.rd[d.b + np] = o1 - o;
+  for (int base = 0; base < n; base += ib() * RV) {
+    int L[RV], np[RV], o[RV], o1[RV];
+#pragma unroll
+    for (int k = 0; k < RV; k++) {
+      int i = base + k * ib() + threadIdx.x;
+      L[k] = i < n ? ldr(&s.B[i]) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < RV; k++) np[k] = L[k] >= 0 ? ldr(&s.E[base + k * ib() + threadIdx.x]) : 0;
+#pragma unroll
+    for (int k = 0; k < RV; k++) {
+      o[k] = L[k] >= 0 ? ldr(&s.C[np[k]]) : 0;
+      o1[k] = L[k] >= 0 && np[k] + 1 < K ? ldr(&s.C[np[k] + 1]) : M;
+    }
+#pragma unroll
+    for (int k = 0; k < RV; k++)
+      if (L[k] >= 0) {
+        int i = base + k * ib() + threadIdx.x;
+        nx.vtx[d.b + np[k]] = ar.vtx[d.b + i];
+        nx.rs[d.b + np[k]] = d.eb + o[k];
+        nx.rd[d.b + np[k]] = o1[k] - o[k];
+      }
   }
-  // rows: each kept entry takes the next slot of its row (order inside a row is free)
-  // (the slot is bounded by the row's counted length)
-  for_entries(s.R, n, s.m, [&](int e) { return s.adjg[e]; }, [&](int i, int, int j) {
-    int L = ldr(&s.B[i]);
-    if (L < 0 || ldr(&s.B[j]) != L) return;
-    int np = ldr(&s.E[i]);
-    int o = ldr(&s.C[np]);
-    int o1 = np + 1 < K ? ldr(&s.C[np + 1]) : M;
-    int slot = atomicAdd(&s.F[np], 1);
-    if (slot < o1 - o) nx.adj[d.eb + o + slot] = ldr(&s.E[j]) - ldr(&s.D[L]);
+  sub_mark(s, 15, &q);
+  // rows: the kept entries of a row run inside a thread's chunk take consecutive slots,
+  // reserved with one atomic on the row's cursor (order inside a row is free; a slot is
+  // bounded by the row's counted length)
+  entry_rounds(s, sh, s.R, n, s.m, [&](int base, int x) {
+    int yv[CH], by[CH], own[CH];
+#pragma unroll
+    for (int i = 0; i < CH; i++) yv[i] = base + i < s.m ? s.adjg[base + i] : 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) by[i] = base + i < s.m ? ldr(&s.B[yv[i]]) : -2;
+    int xend = x + 1 < n ? ldr(&s.R[x + 1]) : s.m;
+    int Lx = ldr(&s.B[x]);
+    uint32_t keep = 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) {
+      int e = base + i;
+      own[i] = -1;
+      if (e < s.m) {
+        if (e >= xend) {
+          do {
+            x++;
+            xend = x + 1 < n ? ldr(&s.R[x + 1]) : s.m;
+          } while (e >= xend);
+          Lx = ldr(&s.B[x]);
+        }
+        own[i] = x;
+        if (Lx >= 0 && by[i] == Lx) keep |= 1u << i;
+      }
+    }
+    // kept entries from i to the end of i's run
+    int suf[CH];
+    suf[CH - 1] = (int)((keep >> (CH - 1)) & 1u);
+#pragma unroll
+    for (int i = CH - 2; i >= 0; i--) suf[i] = (int)((keep >> i) & 1u) + (own[i + 1] == own[i] ? suf[i + 1] : 0);
+    int slot = 0, lim = 0, o = 0, start = 0;
+#pragma unroll
+    for (int i = 0; i < CH; i++) {
+      if (own[i] < 0) continue;
+      if ((i == 0 || own[i] != own[i - 1]) && suf[i] > 0) {
+        int np = ldr(&s.E[own[i]]);
+        o = ldr(&s.C[np]);
+        lim = (np + 1 < K ? ldr(&s.C[np + 1]) : M) - o;
+        start = ldr(&s.D[ldr(&s.B[own[i]])]);
+        slot = atomicAdd(&s.F[np], suf[i]);
+      }
+      if ((keep >> i) & 1u) {
+        if (slot < lim) nx.adj[d.eb + o + slot] = ldr(&s.E[yv[i]]) - start;
+        slot++;
+      }
+    }
   });
+  sub_mark(s, 14, &q);
   // descriptors of the children
   auto child = [&](int i) {
     int cs = ldr(&s.D[i]);
@@ -884,9 +1089,10 @@ NOINL int item_peel(const St &s_in, int k, Sh &sh_in) {
 constexpr int32_t SCANNED = -(1 << 30);  // key of a scanned super-vertex (stays negative)
 
 // Effect of one list entry x -> y whose increment left y's key at nw > 0.
+template <bool GL>
 DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *bl, int *by) {
   int lv = nw < bound ? nw : bound;
-  if (nw <= bound) bit_set(s, nw, y);
+  if (nw <= bound) bit_set<GL>(s, nw, y);
   if (nw == bound) st(&s.B[y], x);          // contractible, first for y: parent
   else if (nw > bound) mark_set(s, e);      // contractible, extra edge
   if (lv > *bl || (lv == *bl && y < *by)) {
@@ -919,7 +1125,7 @@ DEV void scan_entry(const St &s, int x, int y, int nw, int e, int bound, int *bl
 // a valid entry and ignore it.  (During a scan every list array holds at least one entry.)
 DEV int clamp_idx(int e0, int i, int cnt) { return cnt > 0 ? e0 + (i < cnt ? i : cnt - 1) : 0; }
 
-template <bool L16>
+template <bool L16, bool GL>
 DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const int32_t *list,
                    const uint16_t *list16, int bound) {
   const int lane = threadIdx.x;
@@ -939,7 +1145,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
   int e0 = 0, cnt = 0, y = -1;
   for (;;) {
     if (x < 0) {
-      x = __builtin_amdgcn_readfirstlane(bit_pick(s, &jx));
+      x = __builtin_amdgcn_readfirstlane(bit_pick<GL>(s, &jx));
       jx = __builtin_amdgcn_readfirstlane(jx);
       if (x == -2) return -1;
       if (x < 0) break;
@@ -989,7 +1195,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     int bl = -1, by = 0;  // this lane's highest raised level and smallest id there
     if (old >= 0) {
       int nw = old + 1;
-      if (nw <= bound) bit_set(s, nw, y);
+      if (nw <= bound) bit_set<GL>(s, nw, y);
       if (nw == bound) st(&s.B[y], x);          // contractible, first for y: parent
       else if (nw > bound) mark_set(s, e0 + lane);  // contractible, extra edge
       bl = nw < bound ? nw : bound;
@@ -1007,7 +1213,7 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
         for (int k = 0; k < 4; k++) ov[k] = base + 64 * k + lane < cnt ? atomicAdd(&s.A[yv[k]], 1) : -1;
 #pragma unroll
         for (int k = 0; k < 4; k++)
-          if (ov[k] >= 0) scan_entry(s, x, yv[k], ov[k] + 1, e0 + base + 64 * k + lane, bound, &bl, &by);
+          if (ov[k] >= 0) scan_entry<GL>(s, x, yv[k], ov[k] + 1, e0 + base + 64 * k + lane, bound, &bl, &by);
       }
     }
     // only keys raised to jx or above can decide the next vertex; when there are any, one
@@ -1080,7 +1286,7 @@ NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
     for (int x = threadIdx.x; x < n; x += ib()) st(&s.B[x], uf_find(s.B, x));
     __syncthreads();
     sub_mark(s, 20, &q);
-    for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
+    for_entries(s, sh, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
       if (y > x && ld(&s.B[x]) != ld(&s.B[y]) && !mark_get(s, e) && uf_link(s.B, x, y)) {
         mark_set(s, e);
         links++;
@@ -1144,7 +1350,7 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
   }
   __syncthreads();
   sub_mark(s, 20, &q);
-  for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
+  for_entries(s, sh, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
     if (y <= x || mark_get(s, e)) return;
     // (no early exit from the unrolled loop: constant indices keep links[] in registers)
     bool done = false;
@@ -1216,6 +1422,8 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
       // ---- round setup: keys, marks, bitmaps (levels 0..bound)
       int words = (bound + 1) * s.ls;
       for (int w = threadIdx.x; w < words; w += ib()) st(&s.bits[w], (uint64_t)0);
+      if (s.bits1)
+        for (int w = threadIdx.x; w < (bound + 1) * s.nw1; w += ib()) s.bits1[w] = 0;
       for (int x = threadIdx.x; x < n; x += ib()) {
         st(&s.A[x], 0);
         st(&s.B[x], x);
@@ -1223,14 +1431,14 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
       mark_clear(s, total);
       __syncthreads();
       for (int x = threadIdx.x; x < n; x += ib())
-        if (ldr(&s.C[x]) == x) bit_set(s, 0, x);
+        if (ldr(&s.C[x]) == x) bit_set<!LDS>(s, 0, x);
       __syncthreads();
       // ---- maximum-adjacency scan, run by wave 0 alone (no block barrier per step)
       const int32_t *stv = first ? s.R : s.E;
       if (threadIdx.x < 64) {
-        int r = !first    ? scan_round<false>(s, stv, s.D, s.lists, nullptr, bound)
-                : s.adj16 ? scan_round<true>(s, stv, s.D, nullptr, s.adj16, bound)
-                          : scan_round<false>(s, stv, s.D, s.adjg, nullptr, bound);
+        int r = !first    ? scan_round<false, !LDS>(s, stv, s.D, s.lists, nullptr, bound)
+                : s.adj16 ? scan_round<true, !LDS>(s, stv, s.D, nullptr, s.adj16, bound)
+                          : scan_round<false, !LDS>(s, stv, s.D, s.adjg, nullptr, bound);
         if (s.pf && threadIdx.x == 0) {
           atomicAdd(&A.cnt[CNT_PH + 10], (unsigned long long)(r > 0 ? r : 0));
           atomicAdd(&A.cnt[CNT_PH + 12], 1ull);
@@ -1262,9 +1470,9 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
         if (ld(&s.B[x]) != ld(&s.B[y])) uf_unite(s.B, x, y);
       };
       if (first)
-        for_marked_entries(s, stv, n, total, [&](int e) { return adj_at(s, e); }, join);
+        for_marked_entries(s, sh, stv, n, total, [&](int e) { return adj_at(s, e); }, join);
       else
-        for_marked_entries(s, stv, n, total, [&](int e) { return ldr(&s.lists[e]); }, join);
+        for_marked_entries(s, sh, stv, n, total, [&](int e) { return ldr(&s.lists[e]); }, join);
       __syncthreads();
       sub_mark(s, 23, &q);
       for (int x = threadIdx.x; x < n; x += ib())
@@ -1291,7 +1499,7 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
       for (int x = threadIdx.x; x < n; x += ib()) st(&s.D[x], 0);
       mark_clear(s, s.m);
       __syncthreads();
-      for_entries(s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int e, int u) {
+      for_entries(s, sh, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int e, int u) {
         int a = ldr(&s.C[v]);
         if (ldr(&s.C[u]) != a) {
           atomicAdd(&s.D[a], 1);
@@ -1315,7 +1523,7 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
       total = carry;
       __syncthreads();
       sub_mark(s, 27, &q);
-      for_marked_entries(s, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
+      for_marked_entries(s, sh, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int v, int, int u) {
         int a = ldr(&s.C[v]);
         int bb = ldr(&s.C[u]);
         int pos = atomicAdd(&s.A[a], 1);
@@ -1424,6 +1632,8 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
   s.mark = A.sMark + d.eb;
   s.lists = A.sEdge + d.eb;
   s.adj16 = nullptr;
+  s.own = nullptr;
+  s.bits1 = nullptr;
   if constexpr (LDS) {
     s.bits = dyn;
     int32_t *w = (int32_t *)(dyn + (size_t)g.lv * g.ls);
@@ -1448,6 +1658,12 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     s.E = A.sE + d.b;
     s.R = A.sG + d.b;
     s.markbits = nullptr;
+    // The launch's LDS is otherwise unused here: it holds the chunk owners of the entry
+    // passes, then the bitmaps' summary levels (set by every key raise of a scan) when
+    // they fit; items whose summaries do not fit keep none (level searches read L0).
+    if (A.lds_words >= IB_MAX) s.own = (int32_t *)dyn;
+    if (s.l1 && IB_MAX + 2LL * g.lv * g.nw1 <= A.lds_words) s.bits1 = dyn + IB_MAX / 2;
+    else s.l1 = false;
   }
   long long steps = 0, rounds = 0;
   // profile: 1 every item, 2 the first item of each launch, >= 1000 every item with at
