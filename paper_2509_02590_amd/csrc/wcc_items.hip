@@ -1161,6 +1161,11 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
       cnt = ldr(&lenv[x]);
       y = entry(clamp_idx(e0, lane, cnt));
     }
+    // x's bitmap word and list entries are complete before the increments are issued (an
+    // empty asm statement that reads them): the compiler then has no earlier load to wait
+    // for until the increments' results are needed, and the successor's loads below are
+    // issued while the increments are in flight
+    asm volatile("" ::"v"(w0), "v"(y));
     // first 64 increments; their results are used only after the successor's loads
     // below have been issued
     int old = -1;
