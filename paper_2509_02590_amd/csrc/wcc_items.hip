@@ -1156,16 +1156,43 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     const int xw = x >> 6;
     const uint64_t xbit = 1ull << (x & 63);
     uint64_t w0 = ld(&s.bits[__umul24((unsigned)jx, ls) + xw]);
+    // GL: the first L0 word after x's that may hold a member of level jx (from the LDS
+    // summary; a clear summary bit means an empty word) is loaded with x's word: when x's
+    // word holds no other member, the first member there is the successor
+    int wnx = -1;
+    uint64_t wn = 0;
+    if constexpr (GL) {
+      if (s.l1) {
+        const uint64_t *L1 = lvl1<GL>(s, jx);
+        const int i1 = xw >> 6;
+        uint64_t m1 = (L1[i1] & (~0ull << (xw & 63))) & ~(1ull << (xw & 63));
+        if (m1) {
+          wnx = i1 * 64 + __ffsll((long long)m1) - 1;
+        } else {
+          for (int c0 = i1 + 1; c0 < s.nw1; c0 += 64) {
+            uint64_t w1 = c0 + lane < s.nw1 ? L1[c0 + lane] : 0ull;
+            uint64_t b = __ballot(w1 != 0);
+            if (b) {
+              int l = __ffsll((long long)b) - 1;
+              wnx = (c0 + l) * 64 + __ffsll((long long)readlane64(w1, l)) - 1;
+              break;
+            }
+          }
+        }
+        wnx = __builtin_amdgcn_readfirstlane(wnx);
+        if (wnx >= 0 && wnx < s.nw0) wn = ld(&s.bits[__umul24((unsigned)jx, ls) + wnx]);
+      }
+    }
     if (!have) {
       e0 = ldr(&stv[x]);
       cnt = ldr(&lenv[x]);
       y = entry(clamp_idx(e0, lane, cnt));
     }
-    // x's bitmap word and list entries are complete before the increments are issued (an
+    // x's bitmap words and list entries are complete before the increments are issued (an
     // empty asm statement that reads them): the compiler then has no earlier load to wait
     // for until the increments' results are needed, and the successor's loads below are
     // issued while the increments are in flight
-    asm volatile("" ::"v"(w0), "v"(y));
+    asm volatile("" ::"v"(w0), "v"(wn), "v"(y));
     // first 64 increments; their results are used only after the successor's loads
     // below have been issued
     int old = -1;
@@ -1175,7 +1202,8 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
     // in between
     asm volatile("" : "+v"(y));
     uint64_t rest = w0 & ~xbit;
-    int cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1 : -1;
+    int cand = rest ? (x & ~63) + __ffsll((long long)rest) - 1
+                    : wn ? wnx * 64 + __ffsll((long long)wn) - 1 : -1;
     int ce0 = 0, ccnt = 0;
     if (cand >= 0) {
       ce0 = ldr(&stv[cand]);
