@@ -1332,18 +1332,19 @@ NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
   return true;
 }
 
-// The same certificate for t <= TMAX with all forests built in one pass: forest f keeps
-// its union-find in B, A, D, E, C or F (free before the rounds; TMAX = 4 keeps to the
-// arrays an LDS-state item holds in LDS), every vertex first links up to two sampled edges
+// The same certificate for t <= TMAX <= 4 with all forests built in one pass: forest f
+// keeps its union-find in B, A, D or E (free before the rounds, and in LDS for an
+// LDS-state item), every vertex first links up to two sampled edges
 // per forest, and then every unused edge joins the first forest whose trees it connects.
 // One pass over the edges instead of t, but no early stop when a forest cannot span.
 template <int TMAX, bool LDS, bool CL>
 NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
+  static_assert(TMAX >= 1 && TMAX <= 4, "forests 0..3 keep their union-finds in B, A, D, E");
   Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
   const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   const int n = s.n;
   auto P = [&](int f) -> int32_t * {
-    return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : f == 3 ? s.E : f == 4 ? s.C : s.F;
+    return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : s.E;
   };
   unsigned long long q = s.pf ? wall_clock64() : 0;
   mark_clear(s, s.m);

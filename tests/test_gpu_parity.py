@@ -255,7 +255,8 @@ def test_wcc_global_state_items(exec_mode):
     g = gen.chung_lu(60000, 30.0, 2.5, 11, 2000, 2.0, 0.2, 0.15, 0.05, seed=77, intra_mult=1.8)
     try:
         w.set_exec_config(small_lds_kb=4, big_lds_kb=4, big_max_pct=50)
-        # (log2 gives bounds of 5-11, which the global-state certificate covers up to 6)
+        # (log2 gives bounds of 5-11: the one-pass certificate takes bounds up to 4, the
+        # forest-per-pass certificate the larger ones)
         for mode, crit in (("kcore", "log10"), ("paper", "log10"), ("kcore", "log2")):
             want, wrec = oracle.wcc(g.offsets, g.indices, g.membership, mode=mode, criterion=crit)
             got, st, grec = _run(g.offsets, g.indices, g.membership, mode=mode, criterion=crit,
