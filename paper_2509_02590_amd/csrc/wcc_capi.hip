@@ -76,7 +76,7 @@ struct Buf {
 };
 
 enum BufId {
-  B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_POSV, B_DEGIN, B_CURSOR,
+  B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_POSV, B_DEGIN,
   B_ACC, B_MARK, B_RANK, B_TMP, B_DCNT, B_CLSTART, B_CLIDS,
   B_VTX0, B_VTX1, B_RS0, B_RS1, B_RD0, B_RD1, B_ADJ0, B_ADJ1,
   B_SA, B_SB, B_SC, B_SD, B_SE, B_SF, B_SG, B_SEDGE, B_SMARK, B_GBITS,
@@ -267,7 +267,7 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool want_ids,
               hipStream_t s) {
   int64_t N = g->num_vertices;
   size_t n4 = (size_t)(N > 0 ? N : 1) * 4;
-  for (int id : {B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_POSV, B_DEGIN, B_CURSOR,
+  for (int id : {B_KEYS, B_VALS, B_KEYS2, B_VALS2, B_FLAG, B_FLAGSCAN, B_CIDV, B_POSV, B_DEGIN,
                  B_ACC, B_MARK, B_RANK, B_VTX0, B_VTX1, B_RD0, B_RD1, B_SA, B_SB, B_SC, B_SD, B_SE, B_SF,
                  B_SG})
     TRY(w.b[id].ensure(n4));
@@ -302,7 +302,7 @@ int run_front(Workspace &w, const wcc_csr *g, const int32_t *mem, bool want_ids,
   f.cidv = w.b[B_CIDV].as<int32_t>();
   f.posv = w.b[B_POSV].as<int32_t>();
   f.deg_in = w.b[B_DEGIN].as<int32_t>();
-  f.cursor = w.b[B_CURSOR].as<int32_t>();
+  f.stage = w.b[B_ADJ1].as<int32_t>();
   f.tmp = w.b[B_TMP].p;
   f.tmp_bytes = w.b[B_TMP].bytes;
   f.dcnt = w.b[B_DCNT].as<unsigned long long>();

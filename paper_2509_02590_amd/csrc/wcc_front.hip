@@ -217,55 +217,16 @@ __global__ void k_cluster_pos(const int32_t *vtx0, const FrontCounts *fc, int32_
 }
 
 // ---------------------------------------------------------------- compaction
-// deg_in[v] = number of neighbours of v inside v's cluster
+// Two passes, one gather: the staging pass reads every entry and gathers the neighbour's
+// cluster-major position once (the membership test and the local id at once), writing
+// each row's intra entries to the start of the row's own CSR range in a staging array
+// (deg_in[v] counts them and is the row's cursor); the copy pass streams the rows, in
+// cluster-major order, from there into arena 0.  Inside a tile a row's intra entries are
+// counted in LDS first, so each (row, tile) pair reserves its slots with one global atomic.
 template <typename OT>
-__global__ void __launch_bounds__(FB) k_count_intra(const OT *off, const int32_t *idx, int64_t N,
-                                                    int64_t nnz, const int32_t *cidv, int32_t *deg_in) {
-  __shared__ int64_t sh_r[2];
-  __shared__ int64_t cache[FROWS];
-  __shared__ int cnt[FROWS];
-  int64_t e0 = (int64_t)blockIdx.x * FTILE, e1 = e0 + FTILE < nnz ? e0 + FTILE : nnz;
-  bool cached = tile_rows(off, N, e0, e1, sh_r, cache);
-  int64_t r0 = sh_r[0], r1 = sh_r[1];
-  if (cached)
-    for (int64_t i = threadIdx.x; i < r1 - r0 + 1; i += FB) cnt[i] = 0;
-  __syncthreads();
-  for (int i = 0; i < FITEMS; i++) {
-    int64_t e = e0 + (int64_t)i * FB + threadIdx.x;
-    if (e >= e1) break;
-    int64_t r = cached ? row_in_cache(cache, r1 - r0 + 2, e) : row_of(off, r0, r1, e) - r0;
-    int64_t v = r0 + r;
-    int32_t cv = cidv[v];
-    if (cv < 0) continue;
-    if (cidv[idx[e]] == cv) {  // (membership alone: the cluster ids, one gather)
-      if (cached) atomicAdd(&cnt[r], 1);
-      else atomicAdd(&deg_in[v], 1);
-    }
-  }
-  __syncthreads();
-  if (cached)
-    for (int64_t i = threadIdx.x; i < r1 - r0 + 1; i += FB)
-      if (cnt[i]) atomicAdd(&deg_in[r0 + i], cnt[i]);
-}
-
-__global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t N, const FrontCounts *fc,
-                             int32_t *rd0, int64_t *rs0) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  int32_t d = p < fc->na ? deg_in[vtx0[p]] : 0;
-  rd0[p] = d;
-  rs0[p] = d;
-}
-
-// adj0[rs0[pos(v)] + slot] = local id of each intra neighbour.  Slots come from a per-row
-// cursor; inside a tile the row's intra entries are counted in LDS first, so each
-// (row, tile) pair reserves its slots with one global atomic.
-template <typename OT>
-__global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t *idx, int64_t N,
-                                                   int64_t nnz, const int32_t *cidv,
-                                                   const int32_t *posv, const int64_t *cl_start,
-                                                   const int64_t *rs0, int32_t *cursor,
-                                                   int32_t *adj0) {
+__global__ void __launch_bounds__(FB) k_stage_intra(const OT *off, const int32_t *idx, int64_t N, int64_t nnz,
+                                                    const int32_t *cidv, const int32_t *posv,
+                                                    const int64_t *cl_start, int32_t *deg_in, int32_t *stage) {
   __shared__ int64_t sh_r[2];
   __shared__ int64_t cache[FROWS];
   __shared__ int cnt[FROWS];
@@ -282,8 +243,8 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
       int64_t lo = cl_start[cv];
       int32_t pu = posv[idx[e]];
       if (pu < lo || pu >= cl_start[cv + 1]) continue;
-      int32_t slot = atomicAdd(&cursor[v], 1);
-      adj0[rs0[posv[v]] + slot] = (int32_t)(pu - lo);
+      int32_t slot = atomicAdd(&deg_in[v], 1);
+      stage[(int64_t)off[v] + slot] = (int32_t)(pu - lo);
     }
     return;
   }
@@ -307,17 +268,60 @@ __global__ void __launch_bounds__(FB) k_fill_intra(const OT *off, const int32_t 
     slot[i] = atomicAdd(&cnt[r], 1);
   }
   __syncthreads();
-  // one reservation per row of the tile; cache[] is reused for the row's write base
+  // one reservation per row of the tile; cache[] (the row starts) becomes the write base
   for (int r = threadIdx.x; r < nr; r += FB) {
     int c = cnt[r];
-    if (c == 0) continue;
-    int64_t v = r0 + r;
-    cache[r] = rs0[posv[v]] + atomicAdd(&cursor[v], c);
+    if (c) cache[r] += atomicAdd(&deg_in[r0 + r], c);
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < FITEMS; i++)
-    if (val[i] >= 0) adj0[cache[row[i]] + slot[i]] = val[i];
+    if (val[i] >= 0) stage[cache[row[i]] + slot[i]] = val[i];
+}
+
+__global__ void k_gather_deg(const int32_t *vtx0, const int32_t *deg_in, int64_t N, const FrontCounts *fc,
+                             int32_t *rd0, int64_t *rs0) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  int32_t d = p < fc->na ? deg_in[vtx0[p]] : 0;
+  rd0[p] = d;
+  rs0[p] = d;
+}
+
+// adj0[d] for every entry d < E of arena 0: the row of position p (tile rows from rs0,
+// rs0[N] = E) is v = vtx0[p], whose intra entries start at off[v] in the staging array.
+// Grid sized for nnz; tiles at or beyond E exit.
+template <typename OT>
+__global__ void __launch_bounds__(FB) k_copy_intra(const OT *off, const int32_t *vtx0, const int64_t *rs0,
+                                                   int64_t N, const FrontCounts *fc, const int32_t *stage,
+                                                   int32_t *adj0) {
+  __shared__ int64_t sh_r[2];
+  __shared__ int64_t cache[FROWS];
+  __shared__ int64_t src[FROWS];
+  const int64_t E = fc->E;
+  int64_t e0 = (int64_t)blockIdx.x * FTILE;
+  if (e0 >= E) return;
+  int64_t e1 = e0 + FTILE < E ? e0 + FTILE : E;
+  bool cached = tile_rows(rs0, N, e0, e1, sh_r, cache);
+  int64_t r0 = sh_r[0], r1 = sh_r[1];
+  if (!cached) {
+    for (int i = 0; i < FITEMS; i++) {
+      int64_t d = e0 + (int64_t)i * FB + threadIdx.x;
+      if (d >= e1) break;
+      int64_t p = row_of(rs0, r0, r1, d);
+      adj0[d] = stage[(int64_t)off[vtx0[p]] + (d - rs0[p])];
+    }
+    return;
+  }
+  int nr = (int)(r1 - r0 + 1);
+  for (int i = threadIdx.x; i < nr; i += FB) src[i] = (int64_t)off[vtx0[r0 + i]] - cache[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < FITEMS; i++) {
+    int64_t d = e0 + (int64_t)i * FB + threadIdx.x;
+    if (d >= e1) break;
+    adj0[d] = stage[src[row_in_cache(cache, nr + 1, d)] + d];
+  }
 }
 
 __global__ void k_make_items(const int64_t *cl_start, const int32_t *cl_ids, int64_t N, const FrontCounts *fc,
@@ -342,7 +346,10 @@ __global__ void k_make_items(const int64_t *cl_start, const int32_t *cl_ids, int
   if (item_set) item_set[slot] = cl_ids ? cl_ids[c] : (int32_t)c;
 }
 
-__global__ void k_finish_counts(FrontCounts *fc) { fc->K = fc->K32; }
+__global__ void k_finish_counts(FrontCounts *fc, int64_t *rs0, int64_t N) {
+  fc->K = fc->K32;
+  rs0[N] = fc->E;  // (row starts of arena 0 end with the entry count)
+}
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -430,33 +437,34 @@ int front_build(const FrontBufs &f, FrontCounts *fc, int32_t *vtx0, int64_t *cl_
   hipLaunchKernelGGL(k_cluster_pos, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, (const FrontCounts *)fc,
                      f.posv);
   HIP_TRY(hipGetLastError());
-  // counting pass: intra degree per vertex, then row starts by position
+  // staging pass: intra entries at the start of each row's own range (arena 1 is free
+  // until the first split and sized for every entry), intra degree per vertex
   if ((rc = prim_fill32(f.deg_in, 0u, N, s))) return rc;
   if (f.nnz > 0) {
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
-      hipLaunchKernelGGL(k_count_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.deg_in);
+      hipLaunchKernelGGL(k_stage_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx, f.N,
+                         f.nnz, f.cidv, f.posv, cl_start, f.deg_in, f.stage);
     else
-      hipLaunchKernelGGL(k_count_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.deg_in);
+      hipLaunchKernelGGL(k_stage_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx, f.N,
+                         f.nnz, f.cidv, f.posv, cl_start, f.deg_in, f.stage);
   }
+  // row starts by position
   hipLaunchKernelGGL(k_gather_deg, dim3(nblk(N, 256)), dim3(256), 0, s, vtx0, f.deg_in, N,
                      (const FrontCounts *)fc, rd0, rs0);
   HIP_TRY(hipGetLastError());
   rc = prim_excl_scan_i64(rs0, rs0, N, &fc->E, f.tmp, f.tmp_bytes, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(1), 0, s, fc);
-  // fill pass
-  if ((rc = prim_fill32(f.cursor, 0u, N, s))) return rc;
+  hipLaunchKernelGGL(k_finish_counts, dim3(1), dim3(1), 0, s, fc, rs0, N);
+  // copy pass: rows in cluster-major order into arena 0
   if (f.nnz > 0) {
     unsigned g = nblk(f.nnz, FTILE);
     if (f.obits == 32)
-      hipLaunchKernelGGL(k_fill_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.posv, cl_start, rs0, f.cursor, adj0);
+      hipLaunchKernelGGL(k_copy_intra<int32_t>, dim3(g), dim3(FB), 0, s, (const int32_t *)f.off, vtx0, rs0, N,
+                         (const FrontCounts *)fc, f.stage, adj0);
     else
-      hipLaunchKernelGGL(k_fill_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, f.idx,
-                         f.N, f.nnz, f.cidv, f.posv, cl_start, rs0, f.cursor, adj0);
+      hipLaunchKernelGGL(k_copy_intra<int64_t>, dim3(g), dim3(FB), 0, s, (const int64_t *)f.off, vtx0, rs0, N,
+                         (const FrontCounts *)fc, f.stage, adj0);
   }
   if (items)
     hipLaunchKernelGGL(k_make_items, dim3(nblk(N, 256)), dim3(256), 0, s, cl_start, (const int32_t *)cl_ids, N,

@@ -12,7 +12,8 @@ struct FrontBufs {
   int64_t N, nnz;
   uint32_t *keys, *vals, *keys2, *vals2;   // N each
   int32_t *flag, *flag_scan;               // N each
-  int32_t *cidv, *posv, *deg_in, *cursor;  // N each (posv: cluster-major position)
+  int32_t *cidv, *posv, *deg_in;          // N each (posv: cluster-major position)
+  int32_t *stage;                          // nnz words: intra entries by original row
   void *tmp;
   size_t tmp_bytes;
   int32_t *vtab_a, *vtab_b;                // validation: nnz words each (duplicate tables)
