@@ -28,11 +28,11 @@ METRIC = "WCC input edges processed/s (batched vs plain GPU), HBM GB/s; p50/p99 
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per k_items launch on the default workload and form, from rocprofv3 FETCH_SIZE
-# and WRITE_SIZE passes scaled by a known-size copy (profiles/k_items_chunglu-1M-20M_traffic.md).
+# and WRITE_SIZE passes scaled by a known-size copy (profiles/k_items_chunglu-250M-2B_traffic.md).
 # They describe the kernel sources with this digest only: after any change of the item
 # kernel the figure is stale and reported as null until the counters are taken again.
-TRAFFIC = {"sources_sha256_16": "d1db3a418e6e066c", "workload": "chunglu-1M-20M", "exec": "batched",
-           "mode": "kcore", "bytes_per_launch": 52590447.0}
+TRAFFIC = {"sources_sha256_16": "c10668784cee6f3d", "workload": "chunglu-250M-2B", "exec": "batched",
+           "mode": "kcore", "bytes_per_launch": 93781080583.0}
 KERNEL_SOURCES = ["paper_2509_02590_amd/csrc/wcc_items.hip", "paper_2509_02590_amd/csrc/wcc_common.h"]
 
 
