@@ -208,7 +208,7 @@ __global__ void k_cluster_tables(const uint32_t *keys, const uint32_t *vals, con
 
 // posv[v] = v's cluster-major position (its local id plus its cluster's start), -1 for an
 // unassigned vertex (filled beforehand).  u is in cluster c exactly when posv[u] lies in
-// [cl_start[c], cl_start[c+1]), so the fill pass gathers one word per entry (the test and
+// [cl_start[c], cl_start[c+1]), so the staging pass gathers one word per entry (the test and
 // the local id at once).
 __global__ void k_cluster_pos(const int32_t *vtx0, const FrontCounts *fc, int32_t *posv) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
