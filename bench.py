@@ -58,6 +58,7 @@ def workload(name):
     if name == "c2":
         return gen.c2()
     if name == "c4":
+        gen.set_verbose(True)  # (progress lines on stderr during the two-minute generation)
         return gen.c4()
     raise SystemExit("unknown workload %s" % name)
 

@@ -76,8 +76,15 @@ def _load():
         L.gen_export.argtypes = [vp, vp, vp, vp]
         L.gen_free.restype = None
         L.gen_free.argtypes = [vp]
+        L.gen_set_verbose.restype = None
+        L.gen_set_verbose.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
+
+
+def set_verbose(on: bool = True) -> None:
+    """Progress lines on stderr from the generator's phases (each eighth of a phase)."""
+    _load().gen_set_verbose(1 if on else 0)
 
 
 @dataclass

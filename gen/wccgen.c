@@ -122,16 +122,17 @@ typedef struct {
   const char *name;
 } pool_job;
 
-/* With WCCGEN_VERBOSE set, every phase reports each eighth of its tasks on stderr (long
- * generations otherwise print nothing for minutes). */
+/* With WCCGEN_VERBOSE set (or gen_set_verbose(1)), every phase reports each eighth of its
+ * tasks on stderr (long generations otherwise print nothing for minutes). */
+static int g_verbose = -1;
 static int gen_verbose(void) {
-  static int v = -1;
-  if (v < 0) {
+  if (g_verbose < 0) {
     const char *e = getenv("WCCGEN_VERBOSE");
-    v = e && *e && *e != '0';
+    g_verbose = e && *e && *e != '0';
   }
-  return v;
+  return g_verbose;
 }
+void gen_set_verbose(int v) { g_verbose = v ? 1 : 0; }
 
 static void *pool_worker(void *arg) {
   pool_job *j = (pool_job *)arg;

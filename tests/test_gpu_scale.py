@@ -184,13 +184,24 @@ def _sample_clusters(memb, seed, n_small=400, n_mid=6, n_top=3):
                                      rng.choice(mid, min(n_mid, len(mid)), replace=False), top]))
 
 
-def test_c4_sampled_parity():
+def test_c4_sampled_parity(capsys):
     avail = _mem_available()
     if avail < C4_HOST_BYTES:
         pytest.skip("2B-edge workload needs %.0f GiB of host memory, %.0f GiB available"
                     % (C4_HOST_BYTES / 2**30, avail / 2**30))
     import paper_2509_02590_amd as w
-    g, o, a, m = _workload("c4")
+    # (the generator's and this test's progress lines reach the terminal as they happen:
+    # the test runs for minutes)
+    with capsys.disabled():
+        gen.set_verbose(True)
+        try:
+            g, o, a, m = _workload("c4")
+        finally:
+            gen.set_verbose(False)
+        _c4_checks(w, g, o, a, m)
+
+
+def _c4_checks(w, g, o, a, m):
     got, st, rec = w.wcc_run(o, a, m, records_cap=8_000_000)
     got = got.cpu().numpy()
     print("c4 plain: %.0f ms, %d sets, %d records" % (st.ms_total, st.accepted, len(rec)), flush=True)
