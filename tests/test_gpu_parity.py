@@ -247,6 +247,56 @@ def test_wcc_c1_full_kcore():
     assert st.mincuts > 1000
 
 
+def _multi_component_clusters(rng, specs, n_free=50):
+    """Clusters made of several disjoint components (a ring plus random chords each), the
+    vertices of all clusters spread over the id range by a random permutation, so that the
+    components of a cluster interleave in its local ids.  specs: (components, size, extra
+    chords per vertex) per cluster."""
+    n = sum(c * sz for c, sz, _ in specs) + n_free
+    perm = rng.permutation(n)
+    memb = np.full(n, -1, np.int32)
+    edges = []
+    pos = 0
+    for cl, (c, sz, extra) in enumerate(specs):
+        for _ in range(c):
+            ids = perm[pos:pos + sz]
+            pos += sz
+            memb[ids] = cl
+            for i in range(sz):
+                edges.append((ids[i], ids[(i + 1) % sz]))
+            for _ in range(int(extra * sz)):
+                a, b = rng.integers(0, sz, 2)
+                edges.append((ids[a], ids[b]))
+    # a few inter-cluster edges (never inside one cluster: the components stay apart) and
+    # unassigned vertices
+    for _ in range(n // 20):
+        a, b = rng.integers(0, n, 2)
+        if memb[a] != memb[b] or memb[a] < 0:
+            edges.append((a, b))
+    off, adj = csr_from_edges(n, edges)
+    return off, adj, memb
+
+
+@pytest.mark.parametrize("exec_mode", ["plain", "batched"])
+def test_rebuild_child_placement(exec_mode):
+    """Children placed by the packed block scan (up to four per split) and by the
+    single-wavefront walk (more), with state in LDS and, for clusters above the LDS
+    budget, in global memory; the components interleave in each cluster's local ids, so
+    the stable new positions are exercised; against the oracle."""
+    # (PAPER mode on denser components: sparse ones lose their degree-2 vertices one cut
+    # at a time, which the oracle replays slowly)
+    cases = (("kcore", 404, [(4, 30, 1.5), (7, 25, 1.5), (1, 40, 1.5), (3, 4000, 3.0), (6, 2500, 3.0),
+                             (9, 1800, 3.0)]),
+             ("paper", 405, [(4, 30, 3.0), (7, 25, 3.0), (3, 3000, 6.0), (6, 1600, 6.0)]))
+    for mode, seed, specs in cases:
+        off, adj, memb = _multi_component_clusters(np.random.default_rng(seed), specs)
+        want, wrec = oracle.wcc(off, adj, memb, mode=mode)
+        got, st, grec = _run(off, adj, memb, mode=mode, exec_mode=exec_mode)
+        assert np.array_equal(got, want), mode
+        assert _rec_key(grec) == _rec_key(wrec), mode
+        assert len(np.unique(want[want >= 0])) > 10
+
+
 @pytest.mark.parametrize("exec_mode", ["plain", "batched"])
 def test_wcc_global_state_items(exec_mode):
     """Items whose scan state does not fit the large bin's LDS run from global memory:
