@@ -773,6 +773,7 @@ ItemArgs base_args(Workspace &w, const wcc_params &p, int32_t item_cap) {
   A.mode = p.prune_mode;
   A.leaf_batch = p.prune_mode == WCC_PRUNE_PAPER && wcc_k_of(p.criterion, (int64_t)p.s_post + 1, p.lin_num,
                                                               p.lin_den) >= 2;
+  A.low_runs = p.prune_mode == WCC_PRUNE_PAPER;
   A.cnt = w.b[B_DCNT].as<unsigned long long>() + 32;
   return A;
 }

@@ -157,6 +157,9 @@ struct ItemArgs {
   // PAPER mode: items with a vertex of degree 1 are peeled to their 2-core in one batch
   // (every step of the one-at-a-time peel fails its cut: k(s_post + 1) >= 2)
   int32_t leaf_batch;
+  // PAPER mode: runs of single-vertex splits at the minimum degree (>= 2) are removed in
+  // one batch when a certificate shows that every one of them is the canonical cut
+  int32_t low_runs;
   // chained form (batched execution): a workgroup that splits an item processes one of the
   // children itself, next, instead of leaving every child to the next launch
   int32_t chain;

@@ -58,6 +58,7 @@ struct Sh {
   int vi[8];
   int crep[NPACK], cstart[NPACK];  // rebuild: first children's representatives and starts
   int own_lo;                       // entry_rounds: first row of the next round
+  int arr[64];                      // low-degree runs: vertices that entered the current class
   ItemDesc keep;  // chained form: the child this workgroup processes next
   int has_keep;
 };
@@ -1289,11 +1290,14 @@ DEV int scan_round(const St &s, const int32_t *stv, const int32_t *lenv, const i
 // which most edges join one tree and stop at a single comparison.  Uses B (union-find) and the
 // entry marks (used edges); returns false as soon as a forest does not span (the greedy
 // choice can fail even when lambda >= t: the caller then runs the scans).
-template <bool LDS, bool CL>
-NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
+// SUB: the certificate of the subgraph induced by the vertices x with C[x] < 0 (na of
+// them); edges with an endpoint outside are left out.
+template <bool LDS, bool CL, bool SUB = false>
+NOINL bool forest_certificate(const St &s_in, int t, int na, Sh &sh_in) {
   Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
   const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
   const int n = s.n;
+  auto in = [&](int x) { return !SUB || ld(&s.C[x]) < 0; };
   unsigned long long q = s.pf ? wall_clock64() : 0;
   mark_clear(s, s.m);
   for (int f = 0; f < t; f++) {
@@ -1301,15 +1305,16 @@ NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
     __syncthreads();
     int links = 0;
     for (int x = threadIdx.x; x < n; x += ib()) {
+      if (!in(x)) continue;
       // two entries of x's row, at a different place for every forest
       int r0 = ldr(&s.R[x]), dg = row_end(s, x) - r0;
       int e1 = r0 + (2 * f) % dg, e2 = r0 + (2 * f + 1) % dg;
       int y1 = adj_at(s, e1), y2 = adj_at(s, e2);
-      if (y1 > x && !mark_get(s, e1) && uf_link(s.B, x, y1)) {
+      if (y1 > x && in(y1) && !mark_get(s, e1) && uf_link(s.B, x, y1)) {
         mark_set(s, e1);
         links++;
       }
-      if (e2 != e1 && y2 > x && !mark_get(s, e2) && uf_link(s.B, x, y2)) {
+      if (e2 != e1 && y2 > x && in(y2) && !mark_get(s, e2) && uf_link(s.B, x, y2)) {
         mark_set(s, e2);
         links++;
       }
@@ -1320,14 +1325,15 @@ NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
     __syncthreads();
     sub_mark(s, 20, &q);
     for_entries(s, sh, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
-      if (y > x && ld(&s.B[x]) != ld(&s.B[y]) && !mark_get(s, e) && uf_link(s.B, x, y)) {
+      if (y > x && ld(&s.B[x]) != ld(&s.B[y]) && in(x) && in(y) && !mark_get(s, e) &&
+          uf_link(s.B, x, y)) {
         mark_set(s, e);
         links++;
       }
     });
     links = block_sum<IB_MAX>(links, sh.red);  // includes barriers
     sub_mark(s, 21, &q);
-    if (links < n - 1) return false;
+    if (links < na - 1) return false;
   }
   return true;
 }
@@ -1337,8 +1343,8 @@ NOINL bool forest_certificate(const St &s_in, int t, Sh &sh_in) {
 // LDS-state item), every vertex first links up to two sampled edges
 // per forest, and then every unused edge joins the first forest whose trees it connects.
 // One pass over the edges instead of t, but no early stop when a forest cannot span.
-template <int TMAX, bool LDS, bool CL>
-NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
+template <int TMAX, bool LDS, bool CL, bool SUB = false>
+NOINL bool forest_certificate_one(const St &s_in, int t, int na, Sh &sh_in) {
   static_assert(TMAX >= 1 && TMAX <= 4, "forests 0..3 keep their union-finds in B, A, D, E");
   Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
   const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
@@ -1346,6 +1352,7 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
   auto P = [&](int f) -> int32_t * {
     return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : s.E;
   };
+  auto in = [&](int x) { return !SUB || ld(&s.C[x]) < 0; };  // (as for forest_certificate)
   unsigned long long q = s.pf ? wall_clock64() : 0;
   mark_clear(s, s.m);
   for (int x = threadIdx.x; x < n; x += ib()) {
@@ -1358,6 +1365,7 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
 #pragma unroll
   for (int f = 0; f < TMAX; f++) links[f] = 0;
   for (int x = threadIdx.x; x < n; x += ib()) {
+    if (!in(x)) continue;
     int r0 = ldr(&s.R[x]), dg = row_end(s, x) - r0;
 #pragma unroll
     for (int f = 0; f < TMAX; f++) {
@@ -1365,11 +1373,11 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
       // two entries of x's row, at a different place for every forest
       int e1 = r0 + (2 * f) % dg, e2 = r0 + (2 * f + 1) % dg;
       int y1 = adj_at(s, e1), y2 = adj_at(s, e2);
-      if (y1 > x && !mark_get(s, e1) && uf_link(P(f), x, y1)) {
+      if (y1 > x && in(y1) && !mark_get(s, e1) && uf_link(P(f), x, y1)) {
         mark_set(s, e1);
         links[f]++;
       }
-      if (e2 != e1 && y2 > x && !mark_get(s, e2) && uf_link(P(f), x, y2)) {
+      if (e2 != e1 && y2 > x && in(y2) && !mark_get(s, e2) && uf_link(P(f), x, y2)) {
         mark_set(s, e2);
         links[f]++;
       }
@@ -1385,7 +1393,7 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
   __syncthreads();
   sub_mark(s, 20, &q);
   for_entries(s, sh, s.R, n, s.m, [&](int e) { return adj_at(s, e); }, [&](int x, int e, int y) {
-    if (y <= x || mark_get(s, e)) return;
+    if (y <= x || mark_get(s, e) || !in(x) || !in(y)) return;
     // (no early exit from the unrolled loop: constant indices keep links[] in registers)
     bool done = false;
 #pragma unroll
@@ -1403,10 +1411,202 @@ NOINL bool forest_certificate_one(const St &s_in, int t, Sh &sh_in) {
 #pragma unroll
   for (int f = 0; f < TMAX; f++) {
     int l = block_sum<IB_MAX>(links[f], sh.red);  // includes barriers
-    if (f < t && l < n - 1) ok = false;
+    if (f < t && l < na - 1) ok = false;
   }
   sub_mark(s, 21, &q);
   return ok;
+}
+
+// bounds up to TONE: all forests of the certificate in one pass
+constexpr int TONE = 4;
+
+// ---------------------------------------------------------------- PAPER-mode low-degree runs
+// An item H (connected, minimum degree delta >= 2, delta < k(|H|)) whose cut value equals
+// its minimum degree has canonical cut (delta, {smallest vertex of degree delta}): Phase 0
+// sets it and the rounds replace it only by a strictly smaller cut.  The part of size 1 is
+// dropped and the rest is the next item.  So while that equality holds, WCC as printed
+// removes, one item at a time, the smallest vertex of minimum degree.  This computes such
+// a sequence at once and proves the equality for every step:
+//   * the run: v_1, v_2, ... with H_0 = H, H_t = H_{t-1} - v_t, v_t the smallest vertex of
+//     minimum degree d_t in H_{t-1}; it goes on while d_t < k(|H_{t-1}|), |H_{t-1}| >
+//     s_post and d_1 <= d_2 <= ... (a removal that would leave a degree below d_t ends
+//     the run before it);
+//   * adding back a vertex of degree d to a graph of edge connectivity c gives connectivity
+//     at least min(c, d).  Hence lambda(H_{t-1}) >= min(lambda(H_P), d_t, ..., d_P) =
+//     d_t for a non-decreasing run of P steps with lambda(H_P) >= d_P, and lambda <= the
+//     minimum degree gives equality;
+//   * lambda(H_P) >= d_P is certified by d_P edge-disjoint spanning forests of H_P.  If
+//     they are not found, the item is cut as usual (the run was only a proposal).
+// The run is sequential (wave 0).  Degree classes are taken in increasing order: the block
+// lists the class's vertices in id order, and vertices whose degree falls into the class
+// during it wait in sh.arr (up to 64; when full, the class list is rebuilt).
+// Arrays: A degrees, C removal step (-1 = still in H), D the class list, then the suffix
+// minima of the order, E the removal order, F the degrees d_t; B ends as the child's labels.
+// Returns the number of vertices left when the rest goes on (B[i] = its smallest vertex for
+// members, -1 otherwise), 0 when nothing goes on, -1 when no certified run exists.
+template <bool LDS, bool CL>
+NOINL int item_low_run(const ItemArgs &A, const St &s_in, const ItemDesc &d, int dmin, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
+  Arena ar = A.ar[d.depth & 1];
+  ar.vtx = as_glb(ar.vtx);
+  const int n = s.n;
+  auto kof = [&](int sz) { return (int)wcc_k_of(A.crit, sz, A.lin_num, A.lin_den); };
+  for (int i = threadIdx.x; i < n; i += ib()) {
+    st(&s.A[i], row_end(s, i) - ldr(&s.R[i]));
+    st(&s.C[i], -1);
+  }
+  int P = 0, dc = dmin;
+  long long edges = s.m / 2;  // edges of the current set
+  for (;;) {
+    const int size = n - P;
+    if (size <= A.s_post || dc >= kof(size)) break;
+    // the class list: vertices of the current set with degree dc, in id order
+    int carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += ib()) {
+      int i = base + threadIdx.x;
+      bool f = i < n && ld(&s.C[i]) < 0 && ld(&s.A[i]) == dc;
+      int tot;
+      int pre = block_excl_scan<IB_MAX>((int)f, sh.red, &tot);
+      if (f) st(&s.D[carry + pre], i);
+      carry += tot;
+    }
+    const int len = carry;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      int cur = 0, na = 0, status = 0;  // 0 class done, 1 list rebuilt, 2 run ends
+      int p = P;
+      for (;;) {
+        const int sz = n - p;
+        if (sz <= A.s_post || dc >= kof(sz)) {
+          status = 2;
+          break;
+        }
+        int head = cur < len ? ld(&s.D[cur]) : 0x7fffffff;
+        int av = lane < na ? sh.arr[lane] : 0x7fffffff;
+        int amin = wave_min_i(av);
+        int v = head < amin ? head : amin;
+        if (v == 0x7fffffff) break;  // the class is empty
+        // the neighbours still in the set lose one: below dc ends the run, dc joins the class
+        const int e0 = ldr(&s.R[v]), e1 = row_end(s, v);
+        int drop = 0, join = 0;
+        for (int b = e0; b < e1; b += 64) {
+          int e = b + lane;
+          if (e < e1) {
+            int w = adj_at(s, e);
+            if (ld(&s.C[w]) < 0) {
+              int dw = ld(&s.A[w]) - 1;
+              drop += dw < dc;
+              join += dw == dc;
+            }
+          }
+        }
+        if (wave_sum(drop)) {
+          status = 2;
+          break;
+        }
+        const bool from_arr = v != head;
+        if (na - (int)from_arr + wave_sum(join) > 64) {
+          status = 1;
+          break;
+        }
+        if (from_arr) {  // the last waiting vertex takes v's slot
+          int slot = wave_min_i(av == v ? lane : 64);
+          int last = __shfl(av, na - 1, 64);
+          if (lane == slot) sh.arr[slot] = last;
+          na--;
+        } else {
+          cur++;
+        }
+        for (int b = e0; b < e1; b += 64) {
+          int e = b + lane;
+          bool j = false;
+          int w = 0;
+          if (e < e1) {
+            w = adj_at(s, e);
+            if (ld(&s.C[w]) < 0) {
+              int dw = ld(&s.A[w]) - 1;
+              st(&s.A[w], dw);
+              j = dw == dc;
+            }
+          }
+          uint64_t bm = __ballot(j);
+          if (j) sh.arr[na + __popcll(bm & lanemask_lt())] = w;
+          na += __popcll(bm);
+        }
+        if (lane == 0) {
+          st(&s.C[v], p);
+          st(&s.F[p], dc);
+        }
+        p++;
+        // (this wave reads these words again in the next step)
+        __threadfence_block();
+      }
+      if (lane == 0) {
+        sh.vi[0] = p;
+        sh.vi[1] = status;
+      }
+    }
+    __syncthreads();
+    const int p1 = sh.vi[0], status = sh.vi[1];
+    edges -= (long long)dc * (p1 - P);
+    P = p1;
+    if (status == 2) break;
+    if (status == 0) dc++;
+  }
+  __syncthreads();
+  if (P == 0) return -1;
+  // lambda(H_P) >= d_P: d_P edge-disjoint spanning forests of the vertices left
+  const int na = n - P, dP = ld(&s.F[P - 1]);
+  bool ok = na <= 1 || (edges >= (long long)dP * (na - 1) &&
+                        (dP <= TONE ? forest_certificate_one<TONE, LDS, CL, true>(s_in, dP, na, sh)
+                                    : forest_certificate<LDS, CL, true>(s_in, dP, na, sh)));
+  __syncthreads();
+  if (!ok) return -1;
+  // the removal order (E), then the smallest vertex never removed and the suffix minima
+  int cm = 0x7fffffff;
+  for (int i = threadIdx.x; i < n; i += ib()) {
+    int c = ld(&s.C[i]);
+    if (c >= 0) st(&s.E[c], i);
+    else cm = i < cm ? i : cm;
+  }
+  cm = (int)block_min_u64<IB_MAX>((unsigned long long)(uint32_t)cm, sh.redu);
+  int run = cm;
+  for (int top = ((P + ib() - 1) / ib()) * ib(); top > 0; top -= ib()) {
+    int i = top - ib() + threadIdx.x;
+    int v = i < P ? ld(&s.E[i]) : 0x7fffffff;
+    int cmin;
+    int suf = block_suffix_min(v, run, sh, &cmin);
+    if (i < P) st(&s.D[i], suf);
+    run = cmin;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P; i += ib()) {
+    int ni = n - i;
+    wcc_record rc;
+    rc.minv = ar.vtx[d.b + ld(&s.D[i])];
+    rc.n = ni;
+    rc.k = kof(ni);
+    rc.lambda = ld(&s.F[i]);
+    rc.ssize = 1;
+    rc.reserved = 0;
+    rc.shash = vhash(ar.vtx[d.b + ld(&s.E[i])]);
+    if (A.rec) {
+      unsigned long long q = atomicAdd(&A.cnt[CNT_RECORDS], 1ull);
+      if ((long long)q < A.rec_cap) A.rec[q] = rc;
+    }
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&A.cnt[CNT_MINCUTS], (unsigned long long)P);
+    if (P > 1) atomicAdd(&A.cnt[CNT_ITEMS], (unsigned long long)(P - 1));
+  }
+  __syncthreads();
+  if (na <= A.s_post) return 0;
+  for (int i = threadIdx.x; i < n; i += ib()) st(&s.B[i], ld(&s.C[i]) < 0 ? cm : -1);
+  __syncthreads();
+  return na;
 }
 
 // Returns the capped cut value; F[i] = 1 for i in S.  steps/rounds are accumulated.
@@ -1435,10 +1635,9 @@ NOINL int item_mincut(const ItemArgs &A, const St &s_in, const ItemDesc &d, int 
   // (one pass for bounds up to 4; above, one pass per forest, which stops at the first
   // forest that does not span: for items split by a small cut that is cheaper than
   // checking every forest per edge, most of all when the union-finds are in global memory)
-  constexpr int TONE = 4;
   if (bound > 1 && (long long)s.m / 2 >= (long long)bound * (n - 1) &&
-      (bound <= TONE ? forest_certificate_one<TONE, LDS, CL>(s_in, bound, sh)
-                      : forest_certificate<LDS, CL>(s_in, bound, sh))) {
+      (bound <= TONE ? forest_certificate_one<TONE, LDS, CL>(s_in, bound, n, sh)
+                      : forest_certificate<LDS, CL>(s_in, bound, n, sh))) {
     if (s.pf && threadIdx.x == 0) atomicAdd(&A.cnt[CNT_PH + 11], 1ull);
     bound = -bound;  // (certified; restored below)
   }
@@ -1772,7 +1971,7 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
     }
   } else if (d.m == 0) {
     return;  // Alg. 3 tests only sets with at least one edge
-  } else if (A.leaf_batch) {
+  } else if (A.leaf_batch || A.low_runs) {
     // Phase 0's minimum degree: 1 means a run of single-vertex splits (peeled at once)
     int dmin = 0x7fffffff;
     for (int i = threadIdx.x; i < n; i += ib()) {
@@ -1780,10 +1979,19 @@ DEV void process_item_t(const ItemArgs &A, const ItemDesc &d, uint64_t *dyn, int
       dmin = dg < dmin ? dg : dmin;
     }
     dmin = (int)block_min_u64<IB_MAX>((unsigned long long)(uint32_t)dmin, sh.redu);
-    if (dmin == 1) {
+    if (dmin == 1 && A.leaf_batch) {
       if (item_leaf_peel<LDS, CL>(A, s, d, sh) > 0) item_rebuild<LDS, CL>(A, s, d, A.s_post, sh);
       ph_mark(A, s, 9, &pt);
       return;
+    }
+    // a run of single-vertex splits at the minimum degree, removed at once when certified
+    if (A.low_runs && dmin >= 1 && dmin < k && k <= 64) {
+      int left = item_low_run<LDS, CL>(A, s, d, dmin, sh);
+      if (left >= 0) {
+        if (left > 0) item_rebuild<LDS, CL>(A, s, d, A.s_post, sh);
+        ph_mark(A, s, 9, &pt);
+        return;
+      }
     }
   }
   int lam = item_mincut<LDS, CL>(A, s, d, k, sh, &steps, &rounds);

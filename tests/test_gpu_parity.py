@@ -414,3 +414,84 @@ def test_wcc_c1_full_paper():
     g = gen.c1()
     st = _compare(g.offsets, g.indices, g.membership, mode="paper")
     assert st.mincuts > 1000
+
+
+def _low_degree_clusters(rng, n_clusters):
+    """Clusters on which PAPER mode removes vertices of the minimum degree (>= 2) one split
+    at a time: a random core with periphery vertices of degree 2-6 attached to earlier
+    vertices and short paths between vertices (their inner vertices end runs early); some
+    carry a second half joined by one bridge, so that a proposed run is refuted by its
+    certificate (the item's cut is 1, below its minimum degree)."""
+    edges, memb, base = [], [], 0
+    for c in range(n_clusters):
+        n_core = int(rng.integers(20, 160))
+        p = float(rng.uniform(0.08, 0.4))
+        e = [(i, j) for i in range(n_core) for j in range(i + 1, n_core) if rng.random() < p]
+        nxt = n_core
+        for _ in range(int(rng.integers(0, 80))):
+            d = int(rng.choice([2, 3, 4, 5, 6]))
+            e += [(int(u), nxt) for u in rng.choice(nxt, size=min(d, nxt), replace=False)]
+            nxt += 1
+        for _ in range(int(rng.integers(0, 6))):
+            prev = int(rng.integers(0, nxt))
+            for _ in range(int(rng.integers(1, 5))):
+                e.append((prev, nxt))
+                prev, nxt = nxt, nxt + 1
+            e.append((prev, int(rng.integers(0, n_core))))
+        if rng.random() < 0.3:
+            h = n_core // 2
+            e += [(nxt + i, nxt + j) for i in range(h) for j in range(i + 1, h) if rng.random() < p]
+            e.append((0, nxt))
+            nxt += h
+        perm = rng.permutation(nxt)
+        edges += [(base + int(perm[a]), base + int(perm[b])) for a, b in e if a != b]
+        memb += [c] * nxt
+        base += nxt
+    for _ in range(base // 20):   # edges between clusters (dropped by the compaction)
+        u, v = rng.integers(0, base, 2)
+        if memb[u] != memb[v]:
+            edges.append((int(u), int(v)))
+    off, adj = csr_from_edges(base, edges)
+    return off, adj, np.array(memb, np.int32)
+
+
+def _waiting_overflow_cluster(n_pairs=100, n_core=200, p=0.3, seed=5):
+    """One cluster whose run at degree 2 makes more than 64 vertices wait to enter the
+    degree class: vertices 0..n_pairs-1 (degree 2) each join a vertex of degree 3 with a
+    larger id and a core vertex; removing them lowers those to degree 2 while the class
+    list still holds smaller ids.  PAPER mode removes all 2 * n_pairs one at a time."""
+    rng = np.random.default_rng(seed)
+    lo, hi, core = 0, n_pairs, 2 * n_pairs
+    e = [(core + i, core + j) for i in range(n_core) for j in range(i + 1, n_core) if rng.random() < p]
+    for i in range(n_pairs):
+        c1, c2, c3 = (core + int(x) for x in rng.choice(n_core, 3, replace=False))
+        e += [(lo + i, hi + i), (lo + i, c1), (hi + i, c2), (hi + i, c3)]
+    off, adj = csr_from_edges(core + n_core, e)
+    return off, adj, np.zeros(core + n_core, np.int32)
+
+
+@pytest.mark.parametrize("crit", ["log10", "log2", "sqrt"])
+def test_paper_low_runs(crit):
+    """PAPER mode: runs of single-vertex splits at the minimum degree (>= 2), computed in
+    one batch and certified by spanning forests of the rest, against the oracle's one cut
+    at a time; with item state in LDS and in global memory, in both execution forms."""
+    w = _w()
+    rng = np.random.default_rng({"log10": 910, "log2": 911, "sqrt": 912}[crit])
+    cases = [_low_degree_clusters(rng, 40) for _ in range(2)]
+    if crit == "log10":
+        cases.append(_waiting_overflow_cluster())
+    for i, (off, adj, memb) in enumerate(cases):
+        want, wrec = oracle.wcc(off, adj, memb, mode="paper", criterion=crit)
+        for exec_mode, tiny_lds in (("plain", False), ("batched", False), ("plain", True)):
+            try:
+                if tiny_lds:
+                    w.set_exec_config(small_lds_kb=4, big_lds_kb=4, big_max_pct=50)
+                got, st, grec = _run(off, adj, memb, mode="paper", criterion=crit, exec_mode=exec_mode,
+                                     graph=False)
+            finally:
+                w.set_exec_config()
+            assert np.array_equal(got, want), (i, exec_mode, tiny_lds)
+            assert _rec_key(grec) == _rec_key(wrec), (i, exec_mode, tiny_lds)
+            if i == 2:
+                # 200 single-vertex splits in a handful of levels: the run was taken
+                assert len(wrec) > 200 and st.levels < 10, (len(wrec), st.levels)
