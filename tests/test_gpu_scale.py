@@ -2,7 +2,8 @@
 
 * the whole 10M-vertex / 200M-edge workload (clusters up to ~1e5 vertices, bridges nested
   up to three levels deep): every vertex's label and every split record (minv, n, k,
-  lambda, |S|, hash of S), in both execution forms;
+  lambda, |S|, hash of S), in both execution forms; in PAPER mode against digests of the
+  oracle's run, stored in tests/golden (it takes the oracle tens of minutes);
 * clusters of 20k-60k vertices with nested bridges, in both pruning modes and under two
   criteria, so that cut items above 16,384 vertices (summary level of the scan bitmaps)
   and items whose scan state lives in global memory are compared record by record;
@@ -170,6 +171,38 @@ def test_c2_paper_mode_sampled():
         print("gpu paper %s: %.0f ms, %d levels" % (exec_mode, st.ms_total, st.levels), flush=True)
         assert np.array_equal(got, want), (exec_mode, int((got != want).sum()))
         assert _rec_key(rec) == _rec_key(wrec), exec_mode
+
+
+def test_c2_paper_mode_whole_workload():
+    """PAPER mode on the whole 10M-vertex workload, every label and every split record
+    (plain form: each call takes about a minute; the batched form is compared with the
+    oracle on sampled clusters above), against digests of the oracle's own run of it
+    (tests/golden/c2_paper_digest.json, written by make_c2_paper_digest.py next to it:
+    the oracle takes tens of minutes, since it replays the single-vertex splits of the
+    largest clusters one cut at a time)."""
+    import json
+    import sys
+    import paper_2509_02590_amd as w
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(here, "c2_paper_digest.json")) as f:
+        doc = json.load(f)
+    sys.path.insert(0, here)
+    try:
+        from make_c2_paper_digest import membership_digest, records_digest
+    finally:
+        sys.path.remove(here)
+    g, o, a, m = _workload("c2")
+    assert doc["workload"] == g.meta["workload"] and doc["edges"] == g.m
+    for exec_mode in ("plain",):
+        got, st, rec = w.wcc_run(o, a, m, mode="paper", exec_mode=exec_mode, graph=False, records_cap=8_000_000)
+        got = got.cpu().numpy()
+        print("gpu paper %s on the whole workload: %.0f ms, %d levels, %d records (oracle: %.0f s on %d threads)"
+              % (exec_mode, st.ms_total, st.levels, len(rec), doc["oracle_seconds"], doc["oracle_threads"]),
+              flush=True)
+        assert len(rec) == doc["records"], exec_mode
+        assert int((got >= 0).sum()) == doc["labelled_vertices"], exec_mode
+        assert membership_digest(got) == doc["membership_sha256"], exec_mode
+        assert records_digest(rec) == doc["records_sha256"], exec_mode
 
 
 def _sample_clusters(memb, seed, n_small=400, n_mid=6, n_top=3):
