@@ -1420,6 +1420,65 @@ NOINL bool forest_certificate_one(const St &s_in, int t, int na, Sh &sh_in) {
 // bounds up to TONE: all forests of the certificate in one pass
 constexpr int TONE = 4;
 
+// A second packing of t <= 4 edge-disjoint spanning forests, for sets on which the sampled
+// greedy fails: there, vertices of low degree, which need one edge in every forest, lose
+// edges to forests that did not need them.  Here every edge is placed by its endpoint with
+// the shorter row (ties: the smaller id), rows of at most 2t entries first, and each row's
+// edges go to the forests in turn (the next edge starts after the forest the last one
+// joined).  Each edge is handled by one thread only, and every link joins two trees of its
+// forest, so the forests are edge-disjoint and acyclic whatever the interleaving.  SUB as
+// for forest_certificate.  Union-finds in B, A, D, E.
+template <bool LDS, bool CL, bool SUB>
+NOINL bool forest_certificate_rot(const St &s_in, int t, int na, Sh &sh_in) {
+  Sh &sh = *as_lds(&sh_in);  // (the workgroup's shared scratch, in LDS)
+  const St s = typed_st<LDS, CL>(s_in);  // (a typed local copy: its fields stay in registers)
+  const int n = s.n;
+  auto P = [&](int f) -> int32_t * {
+    return f == 0 ? s.B : f == 1 ? s.A : f == 2 ? s.D : s.E;
+  };
+  auto in = [&](int x) { return !SUB || ld(&s.C[x]) < 0; };
+  for (int x = threadIdx.x; x < n; x += ib())
+    for (int f = 0; f < t; f++) st(&P(f)[x], x);
+  __syncthreads();
+  int l0 = 0, l1 = 0, l2 = 0, l3 = 0;
+  for (int phase = 0; phase < 2; phase++) {
+    for (int x = threadIdx.x; x < n; x += ib()) {
+      if (!in(x)) continue;
+      const int r0 = ldr(&s.R[x]), r1 = row_end(s, x), lx = r1 - r0;
+      if ((lx <= 2 * t) != (phase == 0)) continue;
+      int f0 = 0;
+      for (int e = r0; e < r1; e++) {
+        const int y = adj_at(s, e);
+        if (y == x || !in(y)) continue;
+        const int ly = row_end(s, y) - ldr(&s.R[y]);
+        if (ly < lx || (ly == lx && y < x)) continue;  // y places this edge
+        for (int j = 0; j < t; j++) {
+          const int f = f0 + j < t ? f0 + j : f0 + j - t;
+          if (uf_link(P(f), x, y)) {
+            l0 += f == 0;
+            l1 += f == 1;
+            l2 += f == 2;
+            l3 += f == 3;
+            f0 = f + 1 < t ? f + 1 : 0;
+            break;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  bool ok = true;
+  int l = block_sum<IB_MAX>(l0, sh.red);  // (each includes barriers)
+  ok = ok && l >= na - 1;
+  l = block_sum<IB_MAX>(l1, sh.red);
+  ok = ok && (t < 2 || l >= na - 1);
+  l = block_sum<IB_MAX>(l2, sh.red);
+  ok = ok && (t < 3 || l >= na - 1);
+  l = block_sum<IB_MAX>(l3, sh.red);
+  ok = ok && (t < 4 || l >= na - 1);
+  return ok;
+}
+
 // ---------------------------------------------------------------- PAPER-mode low-degree runs
 // An item H (connected, minimum degree delta >= 2, delta < k(|H|)) whose cut value equals
 // its minimum degree has canonical cut (delta, {smallest vertex of degree delta}): Phase 0
@@ -1437,11 +1496,25 @@ constexpr int TONE = 4;
 //     minimum degree gives equality;
 //   * lambda(H_P) >= d_P is certified by d_P edge-disjoint spanning forests of H_P.  If
 //     they are not found, the item is cut as usual (the run was only a proposal).
+// Ears (degree 2, when k(s_post + 1) >= 2): a removal of v at degree 2 that leaves
+// neighbours of degree 1 is kept when those neighbours start paths of degree-2 vertices
+// (x_1, x_2, ... up to an end z of degree >= 3) whose ends keep degree >= 2 afterwards.
+// The one-at-a-time process then peels both paths right after v, smallest leaf first
+// (each a split of cut 1), and stops at the ends; the set before v is the set after the
+// paths plus an ear, whose edge connectivity is at least min(its connectivity, 2).  With
+// lambda >= 2 at the step after the paths (the same argument from the end of the run,
+// where d_max forests certify lambda(H_P) >= d_max, the largest class degree), v's step
+// has lambda = 2 and the leaf steps lambda = 1.  A path that returns to v (the set is a
+// cycle), an end that would fall below degree 2, or a path that would leave s_post or
+// fewer vertices ends the run before v.
 // The run is sequential (wave 0).  Degree classes are taken in increasing order: the block
 // lists the class's vertices in id order, and vertices whose degree falls into the class
-// during it wait in sh.arr (up to 64; when full, the class list is rebuilt).
+// during it wait in sh.arr (up to 64; when full, the class list is rebuilt).  Path
+// vertices removed with an ear leave both (list entries are skipped, the waiting list is
+// compacted).
 // Arrays: A degrees, C removal step (-1 = still in H), D the class list, then the suffix
-// minima of the order, E the removal order, F the degrees d_t; B ends as the child's labels.
+// minima of the order, E the removal order, F the degrees d_t (1 for path vertices); B
+// ends as the child's labels.
 // Returns the number of vertices left when the rest goes on (B[i] = its smallest vertex for
 // members, -1 otherwise), 0 when nothing goes on, -1 when no certified run exists.
 template <bool LDS, bool CL>
@@ -1456,7 +1529,7 @@ NOINL int item_low_run(const ItemArgs &A, const St &s_in, const ItemDesc &d, int
     st(&s.A[i], row_end(s, i) - ldr(&s.R[i]));
     st(&s.C[i], -1);
   }
-  int P = 0, dc = dmin;
+  int P = 0, dc = dmin, dmax = 0;
   long long edges = s.m / 2;  // edges of the current set
   for (;;) {
     const int size = n - P;
@@ -1477,14 +1550,35 @@ NOINL int item_low_run(const ItemArgs &A, const St &s_in, const ItemDesc &d, int
     if (threadIdx.x < 64) {
       const int lane = threadIdx.x;
       int cur = 0, na = 0, status = 0;  // 0 class done, 1 list rebuilt, 2 run ends
-      int p = P;
+      int p = P, rem = 0;                // steps so far, edges removed in this pass
+      // the first neighbour of x still in the set other than `skip` (-1: none skipped)
+      auto next_in_set = [&](int x, int skip) -> int {
+        const int r0 = ldr(&s.R[x]), r1 = row_end(s, x);
+        for (int b = r0; b < r1; b += 64) {
+          int e = b + lane;
+          int w = e < r1 ? adj_at(s, e) : -1;
+          bool f = w >= 0 && w != skip && ld(&s.C[w]) < 0;
+          uint64_t bm = __ballot(f);
+          if (bm) return __shfl(w, (int)__builtin_ctzll(bm), 64);
+        }
+        return -1;
+      };
       for (;;) {
         const int sz = n - p;
         if (sz <= A.s_post || dc >= kof(sz)) {
           status = 2;
           break;
         }
-        int head = cur < len ? ld(&s.D[cur]) : 0x7fffffff;
+        // the first list entry still in the set (path vertices of ears leave it early)
+        int head = 0x7fffffff;
+        while (cur < len) {
+          int h = ld(&s.D[cur]);
+          if (ld(&s.C[h]) < 0) {
+            head = h;
+            break;
+          }
+          cur++;
+        }
         int av = lane < na ? sh.arr[lane] : 0x7fffffff;
         int amin = wave_min_i(av);
         int v = head < amin ? head : amin;
@@ -1503,11 +1597,111 @@ NOINL int item_low_run(const ItemArgs &A, const St &s_in, const ItemDesc &d, int
             }
           }
         }
-        if (wave_sum(drop)) {
-          status = 2;
-          break;
-        }
         const bool from_arr = v != head;
+        if (wave_sum(drop)) {
+          // an ear: v of degree 2 and the paths of degree-2 vertices that start at its
+          // neighbours, checked in full before anything is removed
+          if (!A.leaf_batch || dc != 2) {
+            status = 2;
+            break;
+          }
+          // (a walk that finds no next vertex or outgrows the item, possible only on
+          // input with repeated entries, ends the run)
+          const int nb0 = next_in_set(v, -1), nb1 = nb0 < 0 ? -1 : next_in_set(v, nb0);
+          int z0 = v, z1 = v, L0 = 0, L1 = 0;
+          for (int sd = 0; sd < 2 && nb1 >= 0; sd++) {
+            int prev = v, x = sd ? nb1 : nb0, l = 0;
+            while (x != v && ld(&s.A[x]) == 2) {
+              int nx = next_in_set(x, prev);
+              if (nx < 0 || l >= n) {
+                x = v;
+                break;
+              }
+              prev = x;
+              x = nx;
+              l++;
+            }
+            if (sd) {
+              z1 = x;
+              L1 = l;
+            } else {
+              z0 = x;
+              L0 = l;
+            }
+            if (x == v) break;  // the set is a cycle
+          }
+          bool ok = z0 != v && z1 != v && sz - 1 - L0 - L1 > A.s_post;
+          int zj = 0;  // ends that fall to degree 2 (they join the class)
+          if (ok) {
+            const int a0 = ld(&s.A[z0]), a1 = ld(&s.A[z1]);
+            if (z0 == z1) {
+              ok = a0 >= 4;
+              zj = a0 == 4;
+            } else {
+              zj = (a0 == 3) + (a1 == 3);
+            }
+          }
+          if (!ok) {
+            status = 2;
+            break;
+          }
+          if (na - (int)from_arr + zj > 64) {
+            status = 1;
+            break;
+          }
+          if (from_arr) {  // the last waiting vertex takes v's slot
+            int slot = wave_min_i(av == v ? lane : 64);
+            int last = __shfl(av, na - 1, 64);
+            if (lane == slot) sh.arr[slot] = last;
+            na--;
+          } else {
+            cur++;
+          }
+          if (lane == 0) {
+            st(&s.C[v], p);
+            st(&s.F[p], 2);
+            st(&s.A[nb0], ld(&s.A[nb0]) - 1);
+            st(&s.A[nb1], ld(&s.A[nb1]) - 1);
+          }
+          p++;
+          rem += 2;
+          __threadfence_block();
+          // both paths, smallest leaf first; each path vertex has one neighbour left
+          int h0 = L0 ? nb0 : 0x7fffffff, h1 = L1 ? nb1 : 0x7fffffff;
+          while (h0 != 0x7fffffff || h1 != 0x7fffffff) {
+            const bool first = h0 < h1;
+            const int u = first ? h0 : h1;
+            const int nx = next_in_set(u, -1);
+            if (lane == 0) {
+              st(&s.C[u], p);
+              st(&s.F[p], 1);
+              if (nx >= 0) st(&s.A[nx], ld(&s.A[nx]) - 1);
+            }
+            p++;
+            rem += 1;
+            __threadfence_block();
+            if (first) h0 = --L0 > 0 && nx >= 0 ? nx : 0x7fffffff;
+            else h1 = --L1 > 0 && nx >= 0 ? nx : 0x7fffffff;
+          }
+          // path vertices leave the waiting list; ends that fell to degree 2 join it
+          {
+            int w = lane < na ? sh.arr[lane] : -1;
+            bool keep = w >= 0 && ld(&s.C[w]) < 0;
+            uint64_t km = __ballot(keep);
+            if (keep) sh.arr[__popcll(km & lanemask_lt())] = w;
+            na = __popcll(km);
+          }
+          if (ld(&s.A[z0]) == 2) {
+            if (lane == 0) sh.arr[na] = z0;
+            na++;
+          }
+          if (z1 != z0 && ld(&s.A[z1]) == 2) {
+            if (lane == 0) sh.arr[na] = z1;
+            na++;
+          }
+          __threadfence_block();
+          continue;
+        }
         if (na - (int)from_arr + wave_sum(join) > 64) {
           status = 1;
           break;
@@ -1541,28 +1735,34 @@ NOINL int item_low_run(const ItemArgs &A, const St &s_in, const ItemDesc &d, int
           st(&s.F[p], dc);
         }
         p++;
+        rem += dc;
         // (this wave reads these words again in the next step)
         __threadfence_block();
       }
       if (lane == 0) {
         sh.vi[0] = p;
         sh.vi[1] = status;
+        sh.vi[2] = rem;
       }
     }
     __syncthreads();
     const int p1 = sh.vi[0], status = sh.vi[1];
-    edges -= (long long)dc * (p1 - P);
+    edges -= sh.vi[2];
+    if (p1 > P) dmax = dc;
     P = p1;
     if (status == 2) break;
     if (status == 0) dc++;
   }
   __syncthreads();
   if (P == 0) return -1;
-  // lambda(H_P) >= d_P: d_P edge-disjoint spanning forests of the vertices left
-  const int na = n - P, dP = ld(&s.F[P - 1]);
-  bool ok = na <= 1 || (edges >= (long long)dP * (na - 1) &&
-                        (dP <= TONE ? forest_certificate_one<TONE, LDS, CL, true>(s_in, dP, na, sh)
-                                    : forest_certificate<LDS, CL, true>(s_in, dP, na, sh)));
+  // lambda(H_P) >= d_max: d_max edge-disjoint spanning forests of the vertices left
+  const int na = n - P, dP = dmax;
+  bool ok = na <= 1;
+  if (!ok && edges >= (long long)dP * (na - 1)) {
+    ok = dP <= TONE ? forest_certificate_one<TONE, LDS, CL, true>(s_in, dP, na, sh)
+                    : forest_certificate<LDS, CL, true>(s_in, dP, na, sh);
+    if (!ok && dP <= TONE) ok = forest_certificate_rot<LDS, CL, true>(s_in, dP, na, sh);
+  }
   __syncthreads();
   if (!ok) return -1;
   // the removal order (E), then the smallest vertex never removed and the suffix minima

@@ -470,6 +470,27 @@ def _waiting_overflow_cluster(n_pairs=100, n_core=200, p=0.3, seed=5):
     return off, adj, np.zeros(core + n_core, np.int32)
 
 
+def _ear_clusters(rng, n_clusters):
+    """Clusters from the CPU run test's ear graphs (paths of degree-2 vertices between core
+    vertices, cycles hanging at one vertex, a triangle hanging by a bridge), joined into
+    one graph with a few edges between clusters."""
+    from test_low_runs import _ear_graph
+    edges, memb, base = [], [], 0
+    for c in range(n_clusters):
+        off, adj = _ear_graph(rng)
+        n = len(off) - 1
+        edges += [(base + u, base + int(adj[e])) for u in range(n) for e in range(off[u], off[u + 1])
+                  if u < adj[e]]
+        memb += [c] * n
+        base += n
+    for _ in range(base // 30):
+        u, v = rng.integers(0, base, 2)
+        if memb[u] != memb[v]:
+            edges.append((int(u), int(v)))
+    off, adj = csr_from_edges(base, edges)
+    return off, adj, np.array(memb, np.int32)
+
+
 @pytest.mark.parametrize("crit", ["log10", "log2", "sqrt"])
 def test_paper_low_runs(crit):
     """PAPER mode: runs of single-vertex splits at the minimum degree (>= 2), computed in
@@ -478,7 +499,11 @@ def test_paper_low_runs(crit):
     w = _w()
     rng = np.random.default_rng({"log10": 910, "log2": 911, "sqrt": 912}[crit])
     cases = [_low_degree_clusters(rng, 40) for _ in range(2)]
+    if crit != "sqrt":
+        cases.append(_ear_clusters(rng, 40))
+    overflow = -1
     if crit == "log10":
+        overflow = len(cases)
         cases.append(_waiting_overflow_cluster())
     for i, (off, adj, memb) in enumerate(cases):
         want, wrec = oracle.wcc(off, adj, memb, mode="paper", criterion=crit)
@@ -492,6 +517,6 @@ def test_paper_low_runs(crit):
                 w.set_exec_config()
             assert np.array_equal(got, want), (i, exec_mode, tiny_lds)
             assert _rec_key(grec) == _rec_key(wrec), (i, exec_mode, tiny_lds)
-            if i == 2:
+            if i == overflow:
                 # 200 single-vertex splits in a handful of levels: the run was taken
                 assert len(wrec) > 200 and st.levels < 10, (len(wrec), st.levels)

@@ -175,8 +175,8 @@ def test_c2_paper_mode_sampled():
 
 def test_c2_paper_mode_whole_workload():
     """PAPER mode on the whole 10M-vertex workload, every label and every split record
-    (plain form: each call takes about a minute; the batched form is compared with the
-    oracle on sampled clusters above), against digests of the oracle's own run of it
+    (plain form; the batched form is compared with the oracle on sampled clusters above),
+    against digests of the oracle's own run of it
     (tests/golden/c2_paper_digest.json, written by make_c2_paper_digest.py next to it:
     the oracle takes tens of minutes, since it replays the single-vertex splits of the
     largest clusters one cut at a time)."""
