@@ -279,7 +279,7 @@ def main():
         log("copied %d bytes 5 times" % (4 * n))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(sharding across GPUs is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "served":

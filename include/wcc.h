@@ -57,7 +57,7 @@ extern "C" {
 #define WCC_ECANCELLED -6    /* a served job was cancelled */
 #define WCC_ETIMEOUT -7      /* a served job did not finish in time */
 #define WCC_ENODEV -8        /* no HIP device */
-#define WCC_EUNSUPPORTED -9  /* a size or parameter beyond this build's limits */
+#define WCC_EUNSUPPORTED -9  /* a size or parameter beyond the library's limits */
 
 /* ------------------------------------------------------------------ inputs */
 typedef struct {

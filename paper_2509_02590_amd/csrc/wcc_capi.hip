@@ -1791,7 +1791,7 @@ const char *wcc_strerror(int code) {
     case WCC_ECANCELLED: return "cancelled";
     case WCC_ETIMEOUT: return "timed out";
     case WCC_ENODEV: return "no HIP device";
-    case WCC_EUNSUPPORTED: return "size or parameter beyond this build's limits";
+    case WCC_EUNSUPPORTED: return "size or parameter beyond the library's limits";
   }
   return "unknown error";
 }
